@@ -1,0 +1,431 @@
+/*
+ * kmpp_oracle.c -- plain FP64 CPU oracle for k-means++ seeding and the
+ * nearest-seed assignment that follows it.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or constant table
+ * with the HIP library; both sides implement the method from the paper
+ * ("Parallelization of Kmeans++ using CUDA", arXiv 1908.02136) and the
+ * counter-based generator from its published definition.
+ *
+ * What it computes (paper, Section II, Algorithm 1 "Serial K-means++" and
+ * Algorithm 2 "Parallel K-means++"):
+ *   - the first seed is a uniformly random point;
+ *   - every point keeps the squared distance to its nearest chosen seed,
+ *     initialised to +infinity (O(l) = inf in Algorithm 1);
+ *   - each further seed is point l with probability d_sn(l) / sum_w d_sn(w)
+ *     (the P(n_l) line of Algorithm 1);
+ *   - the sum over all points is taken in double precision (Section II,
+ *     the thrust::reduce paragraph).
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - the random stream is Philox4x32-10 (Salmon et al., SC'11) with
+ *     key = (lo32(seed), hi32(seed)) and counter = (step, instance, 0, 0);
+ *   - u = ((r0 >> 5) * 2^26 + (r1 >> 6)) * 2^-53, a 53-bit uniform in [0,1);
+ *   - first seed i0 = min(floor(u0 * N), N - 1);
+ *   - the draw is the inverse CDF over points in index order:
+ *     t = u_m * S_{N-1}, i_m = min { i : S_i > t } with S the inclusive
+ *     prefix sum of D; if rounding leaves no such i, the last i with D_i > 0;
+ *   - sum D == 0 (fewer than K distinct points): uniform draw, warning code;
+ *   - non-finite sum D: error code;
+ *   - the nearest distance is kept incrementally, D = min(D, delta), which
+ *     equals the paper's recompute-over-all-seeds minimum exactly;
+ *   - precision forms: distances use the dequantised rows, centres are the
+ *     original FP32 rows, and the chosen seed's own D is set to its FP32
+ *     distance to itself, zero.
+ * Everything is FP64; the prefix is summed sequentially in index order in
+ * fixed 65536-row chunks so the result does not depend on thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KMO_OK 0
+#define KMO_W_DEGENERATE 1
+#define KMO_E_INVALID (-1)
+#define KMO_E_NONFINITE (-4)
+#define KMO_CHUNK 65536
+
+/* ---- Philox4x32-10, from Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3" (SC'11), Section 5: four 32-bit words, two
+ * 32x32->64 multiplications per round, Weyl-sequence key schedule. ---- */
+static void kmo_philox_round(uint32_t x[4], const uint32_t k[2]) {
+  const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x[0];
+  const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)x[2];
+  const uint32_t y0 = (uint32_t)(pb >> 32) ^ x[1] ^ k[0];
+  const uint32_t y1 = (uint32_t)pb;
+  const uint32_t y2 = (uint32_t)(pa >> 32) ^ x[3] ^ k[1];
+  const uint32_t y3 = (uint32_t)pa;
+  x[0] = y0;
+  x[1] = y1;
+  x[2] = y2;
+  x[3] = y3;
+}
+
+void kmo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+    kmo_philox_round(x, k);
+  }
+  memcpy(out, x, sizeof(x));
+}
+
+/* 53-bit uniform in [0, 1) for seeding step `step` of instance `inst`. */
+double kmo_uniform(uint64_t seed, uint32_t step, uint32_t inst) {
+  const uint32_t ctr[4] = {step, inst, 0u, 0u};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t r[4];
+  kmo_philox4x32_10(ctr, key, r);
+  const uint64_t hi = (uint64_t)(r[0] >> 5);
+  const uint64_t lo = (uint64_t)(r[1] >> 6);
+  return (double)(hi * 67108864ull + lo) / 9007199254740992.0; /* / 2^53 */
+}
+
+static int kmo_threads(int32_t nthreads) {
+#ifdef _OPENMP
+  return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+/* delta = sum_j (a_j - c_j)^2 in FP64, summed in j order. */
+static double kmo_sqdist(const float* a, const double* c, int32_t d) {
+  double s = 0.0;
+  for (int32_t j = 0; j < d; ++j) {
+    const double t = (double)a[j] - c[j];
+    s += t * t;
+  }
+  return s;
+}
+
+/* Inclusive prefix S of D (FP64), chunked sequential sum; returns S[N-1]. */
+static double kmo_prefix(const double* D, double* S, double* chunk, int64_t N, int nt) {
+  const int64_t nch = (N + KMO_CHUNK - 1) / KMO_CHUNK;
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t q = 0; q < nch; ++q) {
+    const int64_t a = q * KMO_CHUNK, b = (a + KMO_CHUNK < N) ? a + KMO_CHUNK : N;
+    double s = 0.0;
+    for (int64_t i = a; i < b; ++i) s += D[i];
+    chunk[q] = s;
+  }
+  double run = 0.0;
+  for (int64_t q = 0; q < nch; ++q) {
+    const double v = chunk[q];
+    chunk[q] = run; /* exclusive */
+    run += v;
+  }
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t q = 0; q < nch; ++q) {
+    const int64_t a = q * KMO_CHUNK, b = (a + KMO_CHUNK < N) ? a + KMO_CHUNK : N;
+    double s = chunk[q];
+    for (int64_t i = a; i < b; ++i) {
+      s += D[i];
+      S[i] = s;
+    }
+  }
+  return S[N - 1];
+}
+
+/* first i with S[i] > t (S non-decreasing); N if none. */
+int64_t kmo_upper_bound(const double* S, int64_t N, double t) {
+  int64_t lo = 0, hi = N;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (S[mid] > t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+static int64_t kmo_uniform_index(double u, int64_t N) {
+  int64_t i = (int64_t)floor(u * (double)N);
+  return i > N - 1 ? N - 1 : i;
+}
+
+/*
+ * k-means++ seeding, Algorithm 1 with the readings above.
+ *
+ * Xd     [N*d] values distances are computed from (FP32 data or dequantised rows)
+ * Xc     [N*d] values the centres take (FP32 data); may equal Xd
+ * zero_seed_rows  1 for the precision forms: D of the chosen row := 0
+ * replay [K] or NULL: if given, the centre used after step m is replay[m]
+ *        (the GPU's index), while out_idx[m] is still the oracle's own
+ *        draw from the same D; this checks each draw independently.
+ * out_idx [K]   the oracle's draws
+ * out_D   [N]   final nearest squared distance (FP64)
+ * rec     [K*8] or NULL, per step m >= 1:
+ *        T, t, S_{i-1}, S_i (oracle's own i), S_{g-1}, S_g, D_g (g = replay[m],
+ *        or the oracle's own index without replay), u
+ * Returns 0, KMO_W_DEGENERATE, or a negative error.
+ */
+int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, uint64_t seed,
+             uint32_t inst, int32_t zero_seed_rows, const int64_t* replay, int64_t* out_idx,
+             double* out_D, double* rec, int32_t nthreads) {
+  if (!Xd || !Xc || !out_idx || !out_D || N < 1 || d < 1 || K < 1 || K > N) return KMO_E_INVALID;
+  const int nt = kmo_threads(nthreads);
+  const int64_t nch = (N + KMO_CHUNK - 1) / KMO_CHUNK;
+  double* S = (double*)malloc(sizeof(double) * (size_t)N);
+  double* chunk = (double*)malloc(sizeof(double) * (size_t)nch);
+  double* c = (double*)malloc(sizeof(double) * (size_t)d);
+  if (!S || !chunk || !c) {
+    free(S);
+    free(chunk);
+    free(c);
+    return KMO_E_INVALID;
+  }
+  int status = KMO_OK;
+  double* D = out_D;
+
+  const double u0 = kmo_uniform(seed, 0u, inst);
+  out_idx[0] = kmo_uniform_index(u0, N);
+  int64_t prev = replay ? replay[0] : out_idx[0];
+
+  for (int32_t m = 1; m <= K; ++m) {
+    /* centre c_{m-1}: the original row of the previous seed */
+    for (int32_t j = 0; j < d; ++j) c[j] = (double)Xc[prev * (int64_t)d + j];
+    /* D_i = min(D_i, ||x_i - c||^2); the first pass replaces +inf */
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < N; ++i) {
+      const double delta = kmo_sqdist(Xd + i * (int64_t)d, c, d);
+      D[i] = (m == 1 || delta < D[i]) ? delta : D[i];
+    }
+    if (zero_seed_rows) D[prev] = 0.0;
+    if (m == K) break;
+
+    const double T = kmo_prefix(D, S, chunk, N, nt);
+    const double u = kmo_uniform(seed, (uint32_t)m, inst);
+    volatile double tv = u * T; /* one IEEE multiply */
+    const double t = tv;
+    int64_t i;
+    if (!isfinite(T)) {
+      status = KMO_E_NONFINITE;
+      break;
+    } else if (T == 0.0) {
+      i = kmo_uniform_index(u, N);
+      status = KMO_W_DEGENERATE;
+    } else {
+      i = kmo_upper_bound(S, N, t);
+      if (i >= N) { /* t >= S_{N-1} through rounding: last positive D */
+        i = N - 1;
+        while (i > 0 && !(D[i] > 0.0)) --i;
+      }
+    }
+    out_idx[m] = i;
+    const int64_t g = replay ? replay[m] : i;
+    if (rec) {
+      double* r = rec + (size_t)m * 8;
+      r[0] = T;
+      r[1] = t;
+      r[2] = i > 0 ? S[i - 1] : 0.0;
+      r[3] = S[i];
+      r[4] = (g > 0 && g < N) ? S[g - 1] : 0.0;
+      r[5] = (g >= 0 && g < N) ? S[g] : NAN;
+      r[6] = (g >= 0 && g < N) ? D[g] : NAN;
+      r[7] = u;
+    }
+    if (g < 0 || g >= N) {
+      status = KMO_E_INVALID;
+      break;
+    }
+    prev = g;
+  }
+  free(S);
+  free(chunk);
+  free(c);
+  return status;
+}
+
+/* Nearest-seed assignment (output O of Algorithm 1): label = smallest j
+ * attaining min_j ||x_i - c_j||^2, all in FP64.  mind/second nullable. */
+int kmo_assign(const float* X, int64_t N, int32_t d, const float* C, int32_t K, int32_t* labels,
+               double* mind, double* second, int32_t nthreads) {
+  if (!X || !C || !labels || N < 0 || d < 1 || K < 1) return KMO_E_INVALID;
+  const int nt = kmo_threads(nthreads);
+#pragma omp parallel num_threads(nt)
+  {
+    double* c = (double*)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      double best = INFINITY, sec = INFINITY;
+      int32_t bj = 0;
+      for (int32_t j = 0; j < K; ++j) {
+        for (int32_t q = 0; q < d; ++q) c[q] = (double)C[(int64_t)j * d + q];
+        const double v = kmo_sqdist(X + i * (int64_t)d, c, d);
+        if (v < best) {
+          sec = best;
+          best = v;
+          bj = j;
+        } else if (v < sec) {
+          sec = v;
+        }
+      }
+      labels[i] = bj;
+      if (mind) mind[i] = best;
+      if (second) second[i] = sec;
+    }
+    free(c);
+  }
+  return KMO_OK;
+}
+
+/* For sampled checks at full size: FP64 min distance and label of the rows
+ * listed in `rows` against K centres. */
+int kmo_assign_rows(const float* X, int32_t d, const int64_t* rows, int64_t nrows, const float* C,
+                    int32_t K, int32_t* labels, double* mind, double* second) {
+  if (!X || !C || !rows || !labels || !mind || d < 1 || K < 1) return KMO_E_INVALID;
+  double* c = (double*)malloc(sizeof(double) * (size_t)d);
+  for (int64_t r = 0; r < nrows; ++r) {
+    double best = INFINITY, sec = INFINITY;
+    int32_t bj = 0;
+    for (int32_t j = 0; j < K; ++j) {
+      for (int32_t q = 0; q < d; ++q) c[q] = (double)C[(int64_t)j * d + q];
+      const double v = kmo_sqdist(X + rows[r] * (int64_t)d, c, d);
+      if (v < best) {
+        sec = best;
+        best = v;
+        bj = j;
+      } else if (v < sec) {
+        sec = v;
+      }
+    }
+    labels[r] = bj;
+    mind[r] = best;
+    if (second) second[r] = sec;
+  }
+  free(c);
+  return KMO_OK;
+}
+
+/* FP64 squared distance of listed rows to one listed centre each. */
+int kmo_pair_dist(const float* X, int32_t d, const int64_t* rows, int64_t nrows, const float* C,
+                  const int32_t* cols, double* out) {
+  if (!X || !C || !rows || !cols || !out || d < 1) return KMO_E_INVALID;
+  double* c = (double*)malloc(sizeof(double) * (size_t)d);
+  for (int64_t r = 0; r < nrows; ++r) {
+    for (int32_t q = 0; q < d; ++q) c[q] = (double)C[(int64_t)cols[r] * d + q];
+    out[r] = kmo_sqdist(X + rows[r] * (int64_t)d, c, d);
+  }
+  free(c);
+  return KMO_OK;
+}
+
+/* ---- storage formats for the precision forms ----
+ * BF16: the upper half of an IEEE binary32, rounded to nearest, ties to an
+ * even last mantissa bit.  Written from that definition: the two bf16
+ * neighbours of x are compared in FP64. */
+static float kmo_bits_to_float(uint32_t b) {
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+static uint32_t kmo_float_to_bits(float f) {
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  return b;
+}
+
+uint16_t kmo_bf16_encode(float x) {
+  const uint32_t b = kmo_float_to_bits(x);
+  if (isnan(x)) return (uint16_t)((b >> 16) | 0x0040u);
+  const uint32_t lo = b & 0xFFFF0000u;        /* truncation toward zero */
+  if ((b & 0xFFFFu) == 0) return (uint16_t)(lo >> 16);
+  const uint32_t hi = lo + 0x00010000u;       /* next magnitude up */
+  const double dx = fabs((double)x);
+  const double dlo = fabs((double)kmo_bits_to_float(lo));
+  double dhi = fabs((double)kmo_bits_to_float(hi));
+  if (isinf(kmo_bits_to_float(hi))) dhi = 3.402823669209385e38; /* 2^128, the overflow point */
+  const double elo = dx - dlo, ehi = dhi - dx;
+  if (elo < ehi) return (uint16_t)(lo >> 16);
+  if (ehi < elo) return (uint16_t)(hi >> 16);
+  return (uint16_t)(((lo >> 16) & 1u) ? (hi >> 16) : (lo >> 16));
+}
+
+float kmo_bf16_decode(uint16_t h) { return kmo_bits_to_float((uint32_t)h << 16); }
+
+void kmo_bf16_encode_n(const float* x, int64_t n, uint16_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = kmo_bf16_encode(x[i]);
+}
+void kmo_bf16_decode_n(const uint16_t* h, int64_t n, float* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = kmo_bf16_decode(h[i]);
+}
+
+/* FP8 E4M3 "FN" (OCP 8-bit floating point specification): sign, 4-bit
+ * exponent with bias 7, 3-bit mantissa; exponent field 0 encodes subnormals
+ * m * 2^-9; S.1111.111 is NaN; there are no infinities; the largest finite
+ * magnitude is 1.75 * 2^8 = 448. */
+double kmo_fp8_decode(uint8_t q) {
+  const int s = q >> 7, e = (q >> 3) & 15, m = q & 7;
+  double v;
+  if (e == 15 && m == 7)
+    return NAN;
+  else if (e == 0)
+    v = ldexp((double)m, -9);
+  else
+    v = ldexp(1.0 + m / 8.0, e - 7);
+  return s ? -v : v;
+}
+
+/* nearest finite E4M3FN value, ties to even mantissa, saturating at 448:
+ * a direct search over the 127 non-negative finite codes. */
+uint8_t kmo_fp8_encode(double v) {
+  if (isnan(v)) return 0x7F;
+  const uint8_t sign = (v < 0 || (v == 0 && signbit(v))) ? 0x80 : 0x00;
+  const double a = fabs(v);
+  int best = 0;
+  double berr = INFINITY;
+  for (int c = 0; c < 127; ++c) {
+    const double err = fabs(kmo_fp8_decode((uint8_t)c) - a);
+    if (err < berr || (err == berr && (c & 1) == 0 && (best & 1) == 1)) {
+      berr = err;
+      best = c;
+    }
+  }
+  return (uint8_t)(sign | best);
+}
+
+/* Per-row power-of-two scale: e_i = smallest integer e with
+ * amax_i <= 448 * 2^e (e_i = 0 for an all-zero row), clamped to
+ * [-117, 127]; q = E4M3(x / 2^e_i).
+ * The scale is a power of two, so x / 2^e is exact and q * 2^e is exact in
+ * FP32. */
+int32_t kmo_fp8_row_exponent(const float* row, int32_t d) {
+  double amax = 0.0;
+  for (int32_t j = 0; j < d; ++j) {
+    const double a = fabs((double)row[j]);
+    if (a > amax) amax = a;
+  }
+  if (amax == 0.0 || !isfinite(amax)) return 0;
+  int e = -160;
+  while (amax > ldexp(448.0, e)) ++e;
+  /* keep 2^e and the smallest dequantised step (2^(e-9)) normal in FP32 */
+  if (e < -117) e = -117;
+  if (e > 127) e = 127;
+  return e;
+}
+
+void kmo_fp8_quantize_rows(const float* X, int64_t N, int32_t d, uint8_t* q, int8_t* ex) {
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t e = kmo_fp8_row_exponent(X + i * (int64_t)d, d);
+    ex[i] = (int8_t)e;
+    for (int32_t j = 0; j < d; ++j) q[i * (int64_t)d + j] = kmo_fp8_encode(ldexp((double)X[i * (int64_t)d + j], -e));
+  }
+}
+
+void kmo_fp8_dequantize_rows(const uint8_t* q, const int8_t* ex, int64_t N, int32_t d, float* out) {
+  for (int64_t i = 0; i < N; ++i)
+    for (int32_t j = 0; j < d; ++j)
+      out[i * (int64_t)d + j] = (float)ldexp(kmo_fp8_decode(q[i * (int64_t)d + j]), ex[i]);
+}
