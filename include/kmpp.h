@@ -1,0 +1,198 @@
+/*
+ * kmpp.h -- C ABI of libkmpp: k-means++ seeding (D^2 sampling) and
+ * nearest-seed assignment on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of "Parallelization of Kmeans++ using CUDA"
+ * (Heydarpour Shahrezaei and Tavoli, arXiv 1908.02136), Section II:
+ *   Algorithm 1 / Algorithm 2: the first seed is a uniformly random point;
+ *   every point keeps the squared distance D to its nearest chosen seed
+ *   (initially +infinity); each further seed is point l with probability
+ *   D(l) / sum_w D(w); the output is the seed set H and the partition O of
+ *   the points among the seeds.
+ *   Section II (reduction paragraph): the sum of D is taken in double
+ *   precision.
+ * Where the paper is silent this library fixes:
+ *   - random stream: Philox4x32-10 with key (lo32(seed), hi32(seed)) and
+ *     counter (step, instance, 0, 0); u = ((r0>>5)*2^26 + (r1>>6)) * 2^-53;
+ *   - first seed: min(floor(u_0 * N), N-1);
+ *   - draw m: t = u_m * sum(D) (one FP64 multiply); the seed is the first
+ *     index i whose inclusive FP64 prefix of D exceeds t; if rounding leaves
+ *     none, the last index with D > 0;
+ *   - sum(D) == 0 (fewer than K distinct points): uniform index and the
+ *     warning KMPP_W_DEGENERATE; non-finite sum(D): KMPP_E_NONFINITE;
+ *   - assignment ties go to the smallest seed index.
+ *
+ * Conventions for every entry point:
+ *   - all array pointers are DEVICE pointers unless stated otherwise; rows
+ *     are contiguous and row-major; X's base must be 16-byte aligned;
+ *   - `stream` is a hipStream_t (NULL = the null stream); work is enqueued
+ *     asynchronously on it and the call returns without synchronising;
+ *   - the caller owns every buffer, including the workspace, whose size the
+ *     matching *_workspace_bytes function gives; the library allocates no
+ *     device memory in any entry point;
+ *   - arguments are validated before anything is enqueued: a negative
+ *     return means nothing was launched; KMPP_E_HIP means a launch failed;
+ *   - conditions found on the device (non-finite or zero sum of D, an
+ *     expired wait in the batched kernel) are written to a status word in
+ *     the workspace; read it with kmpp_status after the stream is idle;
+ *   - calls that share a workspace must be ordered on one stream.
+ */
+#ifndef KMPP_H_
+#define KMPP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage format of the point rows */
+enum {
+  KMPP_F32 = 0,      /* IEEE binary32 */
+  KMPP_BF16 = 1,     /* bfloat16, round to nearest even from FP32 */
+  KMPP_FP8_E4M3 = 2  /* OCP E4M3FN with one power-of-two scale 2^e per row, e int8 */
+};
+
+/* status codes: 0 ok, > 0 warning (results valid), < 0 error */
+enum {
+  KMPP_OK = 0,
+  KMPP_W_DEGENERATE = 1,    /* sum(D) was 0 at some draw: uniform draw, seeds may repeat */
+  KMPP_E_INVALID = -1,      /* bad sizes, null or misaligned pointer, bad dtype */
+  KMPP_E_WORKSPACE = -2,    /* workspace smaller than *_workspace_bytes */
+  KMPP_E_HIP = -3,          /* a HIP runtime call failed */
+  KMPP_E_NONFINITE = -4,    /* sum(D) not finite (NaN or Inf in X) */
+  KMPP_E_UNSUPPORTED = -5,  /* shape or format not supported */
+  KMPP_E_TIMEOUT = -6       /* a bounded device-side wait expired */
+};
+
+#define KMPP_MAX_D 4096
+
+/* Optional knobs of kmpp_seed (pass NULL for defaults). */
+typedef struct kmpp_seed_opts {
+  uint32_t instance;    /* Philox instance id: counter word 1 (default 0) */
+  int32_t threads;      /* threads per workgroup of the seed pass: 0 (tuned), 256, 512 or 1024 */
+  int32_t rows_per_tile;/* rows per workgroup tile: 0 (tuned) or a positive count */
+  int32_t reserved;
+  float* out_recheck;   /* device [K*2] or NULL.  Precision forms: for each draw m >= 1,
+                           [2m] = D of the drawn row from the quantised rows before it is
+                           committed, [2m+1] = its FP32 nearest distance recomputed from the
+                           original FP32 row against the previous seeds. */
+  void* step_events;    /* host array of K+1 hipEvent_t or NULL: recorded on `stream` before
+                           the first pass and after each of the K passes (profiling only) */
+} kmpp_seed_opts;
+
+/*
+ * k-means++ seeding (paper, Section II, Algorithms 1 and 2).
+ *
+ * X            FP32 [N, d]: the points; seeds (centres) are always copied
+ *              from these original rows
+ * N, d, K      1 <= K <= N <= 2^31 - 1, 1 <= d <= KMPP_MAX_D
+ * seed         Philox key
+ * out_centers  FP32 [K, d]: the chosen rows, in draw order (required)
+ * out_D        FP32 [N] or NULL: the final squared distance of every point to
+ *              its nearest seed (the D array lives in the workspace if NULL)
+ * out_idx      int64 [K] or NULL: the chosen row indices
+ * Xq, Xq_exp   precision forms only (dtype != KMPP_F32): the quantised rows
+ *              the distance passes read (BF16 or FP8 [N, d], from
+ *              kmpp_quantize) and, for FP8, the int8 [N] row exponents; the
+ *              drawn seed's own D is then set to 0, its FP32 distance to
+ *              itself; NULL for KMPP_F32
+ * opts         NULL or knobs above
+ * Returns KMPP_OK or an error from argument checking / launching.
+ * Work per call: K passes over the rows, one per seed; pass m < K also draws
+ * seed m.
+ */
+size_t kmpp_seed_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype);
+int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, float* out_centers,
+              float* out_D, int64_t* out_idx, const void* Xq, const int8_t* Xq_exp, int32_t dtype,
+              const kmpp_seed_opts* opts, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Nearest-seed assignment: the partition O of the paper's Algorithm 1.
+ *
+ * X            [N, d] rows in `dtype` (FP32, BF16 or FP8 with X_exp)
+ * C            FP32 [K, d] seeds
+ * out_labels   int32 [N]: index of the nearest seed; ties -> smallest index
+ * out_mind     FP32 [N] or NULL: squared distance to that seed, direct form
+ * Scores ||c||^2 - 2<x,c> come from matrix-core products with FP32
+ * accumulation; rows whose best and second-best scores are closer than the
+ * product's error bound are re-evaluated in the direct FP32 form.
+ * Distances use the dequantised rows for BF16/FP8.
+ */
+size_t kmpp_assign_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype);
+int kmpp_assign(const void* X, const int8_t* X_exp, int32_t dtype, const float* C, int64_t N, int32_t d,
+                int32_t K, int32_t* out_labels, float* out_mind, void* workspace, size_t ws_bytes,
+                void* stream);
+
+/*
+ * Storage formats for the precision forms.
+ * KMPP_BF16:     Xq uint16 [N, d] = bf16(X), round to nearest even; Xq_exp unused (NULL)
+ * KMPP_FP8_E4M3: e_i = smallest integer e with max_j |X_ij| <= 448 * 2^e (0 for an
+ *                all-zero row), clamped to [-117, 127]; Xq_exp int8 [N] = e_i;
+ *                Xq uint8 [N, d] = E4M3FN(X_ij * 2^-e_i), round to nearest even.
+ * Dequantised values (q * 2^e) are exact in FP32.
+ */
+int kmpp_quantize(const float* X, int64_t N, int32_t d, int32_t dtype, void* Xq, int8_t* Xq_exp,
+                  void* stream);
+
+/* One independent seeding instance of the batched form. */
+typedef struct kmpp_instance {
+  const float* X;       /* FP32 [N, d], 16-byte aligned */
+  int64_t N;
+  int32_t d;
+  int32_t K;
+  float* out_centers;   /* FP32 [K, d] */
+  float* out_D;         /* FP32 [N] or NULL */
+  int64_t* out_idx;     /* int64 [K] or NULL */
+} kmpp_instance;
+
+/*
+ * Batched form: n_inst independent seedings (instance b uses Philox
+ * instance id b) run by ONE persistent kernel.  Each instance is handled by
+ * a gang of workgroups (one workgroup for small instances) that meets at a
+ * device-side barrier per seed; gangs are scheduled longest-first by a
+ * host planner onto the co-resident workgroups.
+ *
+ * inst         HOST array [n_inst]
+ * kmpp_seed_batched_prepare: plans the schedule and uploads the descriptor
+ *              table into the workspace (a synchronous host-to-device copy);
+ * kmpp_seed_batched_launch:  enqueues only kernel launches and so may be
+ *              captured into a graph and replayed;
+ * kmpp_seed_batched:         prepare + launch.
+ * Status: KMPP_E_TIMEOUT if a gang barrier wait expired (results undefined).
+ */
+size_t kmpp_batched_workspace_bytes(const kmpp_instance* inst, int32_t n_inst);
+int kmpp_seed_batched_prepare(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, void* workspace,
+                              size_t ws_bytes, void* stream);
+int kmpp_seed_batched_launch(void* workspace, void* stream);
+int kmpp_seed_batched(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, void* workspace,
+                      size_t ws_bytes, void* stream);
+
+/* Status word written by the device (KMPP_OK, KMPP_W_DEGENERATE,
+ * KMPP_E_NONFINITE, KMPP_E_TIMEOUT).  Synchronises `stream`, then copies the
+ * word of `workspace` (as passed to kmpp_seed / kmpp_seed_batched) into
+ * *out.  Returns KMPP_OK or KMPP_E_HIP. */
+int kmpp_status(const void* workspace, void* stream, int32_t* out);
+
+/* Graph capture helpers: capture the work a sequence of calls enqueues on
+ * `stream` into an executable HIP graph and replay it.  The captured calls
+ * must not be _prepare calls. */
+typedef struct kmpp_graph_s* kmpp_graph;
+int kmpp_graph_begin(void* stream);
+int kmpp_graph_end(void* stream, kmpp_graph* out);
+int kmpp_graph_launch(kmpp_graph g, void* stream);
+int kmpp_graph_destroy(kmpp_graph g);
+
+/* Tuning table: text lines "seed <dtype> <d> <threads> <rows_per_tile>"
+ * override the built-in choices for the seed pass.  Returns the number of
+ * entries read or KMPP_E_INVALID. */
+int kmpp_tune_load(const char* path);
+
+const char* kmpp_strerror(int code);
+int kmpp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMPP_H_ */

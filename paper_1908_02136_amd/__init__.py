@@ -1,0 +1,282 @@
+"""Python binding of libkmpp: k-means++ seeding and nearest-seed assignment
+on MI355X (gfx950).
+
+Argument marshalling only.  Every step of the seeding loop and of the
+assignment runs in the library's HIP kernels; PyTorch supplies device memory
+and the current stream.  The functions carry the C entry points' names
+(``include/kmpp.h``) and take CUDA tensors; outputs are allocated here with
+``torch.empty`` when not passed in.  There is no CPU fallback: if the
+library is not built, or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkmpp.so")
+TUNE_PATH = os.path.join(HERE, "tune_table.txt")
+
+KMPP_F32, KMPP_BF16, KMPP_FP8_E4M3 = 0, 1, 2
+DTYPES = {"f32": KMPP_F32, "bf16": KMPP_BF16, "fp8": KMPP_FP8_E4M3}
+OK, W_DEGENERATE = 0, 1
+E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT = -1, -2, -3, -4, -5, -6
+MAX_D = 4096
+
+# Every symbol the header declares (checked by the test suite).
+SYMBOLS = [
+    "kmpp_seed_workspace_bytes", "kmpp_seed", "kmpp_assign_workspace_bytes", "kmpp_assign", "kmpp_quantize",
+    "kmpp_batched_workspace_bytes", "kmpp_seed_batched_prepare", "kmpp_seed_batched_launch",
+    "kmpp_seed_batched", "kmpp_status", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
+    "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_strerror", "kmpp_version",
+]
+
+
+class KmppError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else f"{strerror(code)} ({code})")
+
+
+class SeedOpts(ctypes.Structure):
+    _fields_ = [("instance", ctypes.c_uint32), ("threads", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("out_recheck", ctypes.c_void_p), ("step_events", ctypes.c_void_p)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("N", ctypes.c_int64), ("d", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("out_centers", ctypes.c_void_p), ("out_D", ctypes.c_void_p), ("out_idx", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libkmpp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    L.kmpp_seed_workspace_bytes.argtypes = [i64, i32, i32, i32]
+    L.kmpp_seed_workspace_bytes.restype = sz
+    L.kmpp_seed.argtypes = [P, i64, i32, i32, u64, P, P, P, P, P, i32, ctypes.POINTER(SeedOpts), P, sz, P]
+    L.kmpp_seed.restype = ctypes.c_int
+    L.kmpp_assign_workspace_bytes.argtypes = [i64, i32, i32, i32]
+    L.kmpp_assign_workspace_bytes.restype = sz
+    L.kmpp_assign.argtypes = [P, P, i32, P, i64, i32, i32, P, P, P, sz, P]
+    L.kmpp_assign.restype = ctypes.c_int
+    L.kmpp_quantize.argtypes = [P, i64, i32, i32, P, P, P]
+    L.kmpp_quantize.restype = ctypes.c_int
+    L.kmpp_batched_workspace_bytes.argtypes = [ctypes.POINTER(Instance), i32]
+    L.kmpp_batched_workspace_bytes.restype = sz
+    L.kmpp_seed_batched_prepare.argtypes = [ctypes.POINTER(Instance), i32, u64, P, sz, P]
+    L.kmpp_seed_batched_prepare.restype = ctypes.c_int
+    L.kmpp_seed_batched_launch.argtypes = [P, P]
+    L.kmpp_seed_batched_launch.restype = ctypes.c_int
+    L.kmpp_seed_batched.argtypes = [ctypes.POINTER(Instance), i32, u64, P, sz, P]
+    L.kmpp_seed_batched.restype = ctypes.c_int
+    L.kmpp_status.argtypes = [P, P, ctypes.POINTER(i32)]
+    L.kmpp_status.restype = ctypes.c_int
+    L.kmpp_graph_begin.argtypes = [P]
+    L.kmpp_graph_begin.restype = ctypes.c_int
+    L.kmpp_graph_end.argtypes = [P, ctypes.POINTER(P)]
+    L.kmpp_graph_end.restype = ctypes.c_int
+    L.kmpp_graph_launch.argtypes = [P, P]
+    L.kmpp_graph_launch.restype = ctypes.c_int
+    L.kmpp_graph_destroy.argtypes = [P]
+    L.kmpp_graph_destroy.restype = ctypes.c_int
+    L.kmpp_tune_load.argtypes = [ctypes.c_char_p]
+    L.kmpp_tune_load.restype = ctypes.c_int
+    L.kmpp_strerror.argtypes = [ctypes.c_int]
+    L.kmpp_strerror.restype = ctypes.c_char_p
+    L.kmpp_version.argtypes = []
+    L.kmpp_version.restype = ctypes.c_int
+    if os.path.exists(TUNE_PATH):
+        L.kmpp_tune_load(TUNE_PATH.encode())
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().kmpp_strerror(int(code)).decode()
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        raise KmppError(code, what)
+    return code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("libkmpp takes contiguous CUDA (HIP) tensors")
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+# ---------------------------------------------------------------- seeding
+def kmpp_seed_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> int:
+    return int(lib().kmpp_seed_workspace_bytes(N, d, K, dtype))
+
+
+def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D=None, out_idx=None, Xq=None,
+              Xq_exp=None, dtype: int = KMPP_F32, instance: int = 0, threads: int = 0, rows_per_tile: int = 0,
+              out_recheck=None, step_events=None, ws=None, stream=None):
+    """k-means++ seeding of the rows of X (FP32 [N, d]).  Returns
+    (idx int64 [K], centers FP32 [K, d], D FP32 [N], workspace)."""
+    _require_cuda(X, Xq, Xq_exp)
+    N, d = X.shape
+    dev = X.device
+    out_centers = torch.empty((K, d), dtype=torch.float32, device=dev) if out_centers is None else out_centers
+    out_D = torch.empty(N, dtype=torch.float32, device=dev) if out_D is None else out_D
+    out_idx = torch.empty(K, dtype=torch.int64, device=dev) if out_idx is None else out_idx
+    if ws is None:
+        ws = workspace(kmpp_seed_workspace_bytes(N, d, K, dtype), dev)
+    opts = SeedOpts(instance, threads, rows_per_tile, 0,
+                    None if out_recheck is None else out_recheck.data_ptr(), step_events)
+    rc = lib().kmpp_seed(_ptr(X), N, d, K, seed, _ptr(out_centers), _ptr(out_D), _ptr(out_idx), _ptr(Xq),
+                         _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "kmpp_seed")
+    return out_idx, out_centers, out_D, ws
+
+
+def kmpp_status(ws: torch.Tensor, stream=None) -> int:
+    out = ctypes.c_int32(0)
+    _check(lib().kmpp_status(_ptr(ws), _stream(stream), ctypes.byref(out)), "kmpp_status")
+    return int(out.value)
+
+
+# ---------------------------------------------------------------- formats
+def kmpp_quantize(X: torch.Tensor, dtype: int, stream=None):
+    """Returns (Xq, Xq_exp): torch.bfloat16 [N, d] (exp None) or torch.float8_e4m3fn
+    [N, d] with int8 [N] row exponents."""
+    _require_cuda(X)
+    N, d = X.shape
+    if dtype == KMPP_BF16:
+        Xq = torch.empty((N, d), dtype=torch.bfloat16, device=X.device)
+        E = None
+    else:
+        Xq = torch.empty((N, d), dtype=torch.float8_e4m3fn, device=X.device)
+        E = torch.empty(N, dtype=torch.int8, device=X.device)
+    _check(lib().kmpp_quantize(_ptr(X), N, d, dtype, _ptr(Xq), _ptr(E), _stream(stream)), "kmpp_quantize")
+    return Xq, E
+
+
+# ---------------------------------------------------------------- assignment
+def kmpp_assign_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> int:
+    return int(lib().kmpp_assign_workspace_bytes(N, d, K, dtype))
+
+
+def kmpp_assign(X: torch.Tensor, C: torch.Tensor, *, X_exp=None, dtype: int = KMPP_F32, out_labels=None,
+                out_mind=None, ws=None, stream=None):
+    """Nearest seed of every row.  X is [N, d] in `dtype` (FP32, BF16 as
+    uint16, FP8 as uint8 with X_exp).  Returns (labels int32 [N], mind FP32 [N], ws)."""
+    _require_cuda(X, C, X_exp)
+    N, d = X.shape
+    K = C.shape[0]
+    dev = X.device
+    out_labels = torch.empty(N, dtype=torch.int32, device=dev) if out_labels is None else out_labels
+    out_mind = torch.empty(N, dtype=torch.float32, device=dev) if out_mind is None else out_mind
+    if ws is None:
+        ws = workspace(kmpp_assign_workspace_bytes(N, d, K, dtype), dev)
+    rc = lib().kmpp_assign(_ptr(X), _ptr(X_exp), dtype, _ptr(C), N, d, K, _ptr(out_labels), _ptr(out_mind),
+                           _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "kmpp_assign")
+    return out_labels, out_mind, ws
+
+
+# ---------------------------------------------------------------- batched
+def _instances(Xs, Ks, outs):
+    arr = (Instance * len(Xs))()
+    for b, (X, K, (C, D, I)) in enumerate(zip(Xs, Ks, outs)):
+        arr[b] = Instance(X.data_ptr(), X.shape[0], X.shape[1], K, C.data_ptr(),
+                          None if D is None else D.data_ptr(), None if I is None else I.data_ptr())
+    return arr
+
+
+def kmpp_batched_workspace_bytes(Xs, Ks) -> int:
+    outs = [(X, None, None) for X in Xs]  # pointers are not read for sizing
+    return int(lib().kmpp_batched_workspace_bytes(_instances(Xs, Ks, outs), len(Xs)))
+
+
+def kmpp_seed_batched_prepare(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stream=None):
+    """Plan and upload a batch.  Returns (outs, ws) with outs[b] = (centers, D, idx)."""
+    _require_cuda(*Xs)
+    dev = Xs[0].device
+    if outs is None:
+        outs = [(torch.empty((K, X.shape[1]), dtype=torch.float32, device=dev),
+                 torch.empty(X.shape[0], dtype=torch.float32, device=dev),
+                 torch.empty(K, dtype=torch.int64, device=dev)) for X, K in zip(Xs, Ks)]
+    arr = _instances(Xs, Ks, outs)
+    if ws is None:
+        ws = workspace(lib().kmpp_batched_workspace_bytes(arr, len(Xs)), dev)
+    _check(lib().kmpp_seed_batched_prepare(arr, len(Xs), seed, _ptr(ws), ws.numel(), _stream(stream)),
+           "kmpp_seed_batched_prepare")
+    return outs, ws
+
+
+def kmpp_seed_batched_launch(ws: torch.Tensor, stream=None):
+    _check(lib().kmpp_seed_batched_launch(_ptr(ws), _stream(stream)), "kmpp_seed_batched_launch")
+
+
+def kmpp_seed_batched(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stream=None):
+    outs, ws = kmpp_seed_batched_prepare(Xs, Ks, seed, outs=outs, ws=ws, stream=stream)
+    kmpp_seed_batched_launch(ws, stream=stream)
+    return outs, ws
+
+
+# ---------------------------------------------------------------- graphs
+class Graph:
+    """Capture what the calls inside ``with g.capture():`` enqueue on the
+    current stream into a HIP graph; ``g.launch()`` replays it."""
+
+    def __init__(self):
+        self.h = ctypes.c_void_p(None)
+
+    def capture(self, stream=None):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_):
+                _check(lib().kmpp_graph_begin(_stream(stream)), "kmpp_graph_begin")
+
+            def __exit__(self_, *exc):
+                _check(lib().kmpp_graph_end(_stream(stream), ctypes.byref(g.h)), "kmpp_graph_end")
+                return False
+        return _Ctx()
+
+    def launch(self, stream=None):
+        _check(lib().kmpp_graph_launch(self.h, _stream(stream)), "kmpp_graph_launch")
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.kmpp_graph_destroy(self.h)
+            self.h = ctypes.c_void_p(None)
+
+
+def kmpp_tune_load(path: str) -> int:
+    return _check(lib().kmpp_tune_load(path.encode()), "kmpp_tune_load")
+
+
+def kmpp_version() -> int:
+    return int(lib().kmpp_version())

@@ -1,0 +1,296 @@
+// api.hip -- the C ABI of libkmpp (declared in include/kmpp.h): argument
+// checks, workspace carving, kernel choice and launch order.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "kmpp_dev.h"
+#include "kmpp_impl.h"
+
+namespace kmpp {
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+int elem_bytes(int dtype) { return dtype == KMPP_F32 ? 4 : dtype == KMPP_BF16 ? 2 : 1; }
+bool valid_dtype(int dtype) { return dtype == KMPP_F32 || dtype == KMPP_BF16 || dtype == KMPP_FP8_E4M3; }
+
+// ---- tuning table: (dtype, d) -> (threads, rows_per_tile)
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
+
+bool tuned(int dtype, int d, int* threads, int* rpt) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({dtype, d});
+  if (it == g_tune.end()) return false;
+  *threads = it->second.first;
+  *rpt = it->second.second;
+  return true;
+}
+
+struct SeedLayout {
+  size_t tsum, D, idx, total;
+};
+
+SeedLayout seed_layout(int64_t N, int K) {
+  SeedLayout L;
+  size_t off = sizeof(Ctl);
+  L.tsum = off;
+  off += align256(sizeof(double) * (size_t)std::min<int64_t>(N, kMaxTiles));
+  L.D = off;
+  off += align256(sizeof(float) * (size_t)N);
+  L.idx = off;
+  off += align256(sizeof(int64_t) * (size_t)K);
+  L.total = off;
+  return L;
+}
+
+const SeedVariant* pick_seed_variant(int dtype, int d, int nt) {
+  const auto& vs = seed_variants();
+  const int eb = elem_bytes(dtype);
+  for (const auto& v : vs)
+    if (v.fmt == dtype && v.nt == nt && v.dexact == d && (d * eb) % v.cb == 0) return &v;
+  const SeedVariant* best = nullptr;
+  for (const auto& v : vs)
+    if (v.fmt == dtype && v.nt == nt && v.dexact < 0 && -v.dexact >= d)
+      if (!best || -v.dexact < -best->dexact) best = &v;
+  return best;
+}
+
+}  // namespace
+
+int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, const SeedVariant** var,
+                     int* rpt_out, int* ntiles_out) {
+  int nt = 256, rpt = 0;
+  int tnt, trpt;
+  if (tuned(dtype, d, &tnt, &trpt)) {
+    nt = tnt;
+    rpt = trpt;
+  }
+  if (opts && opts->threads) nt = opts->threads;
+  if (opts && opts->rows_per_tile > 0) rpt = opts->rows_per_tile;
+  if (nt != 256 && nt != 512) return KMPP_E_UNSUPPORTED;
+  const SeedVariant* v = pick_seed_variant(dtype, d, nt);
+  if (!v) return KMPP_E_UNSUPPORTED;
+  const int64_t it = v->rows_per_iter;
+  if (rpt <= 0) {
+    // about 64 KiB of rows per tile
+    const int64_t row_bytes = (int64_t)d * elem_bytes(dtype);
+    rpt = (int)std::max<int64_t>(it, (65536 / std::max<int64_t>(1, row_bytes)) / it * it);
+  }
+  int64_t r = ((int64_t)rpt + it - 1) / it * it;
+  const int64_t min_r = (N + kMaxTiles - 1) / kMaxTiles;
+  if (r < min_r) r = (min_r + it - 1) / it * it;
+  if (r > (int64_t)1 << 30) return KMPP_E_UNSUPPORTED;
+  *var = v;
+  *rpt_out = (int)r;
+  *ntiles_out = (int)((N + r - 1) / r);
+  return KMPP_OK;
+}
+
+}  // namespace kmpp
+
+using namespace kmpp;
+
+extern "C" {
+
+size_t kmpp_seed_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype) {
+  if (N < 1 || K < 1 || K > N || d < 1 || d > KMPP_MAX_D || !valid_dtype(dtype)) return 0;
+  return seed_layout(N, K).total;
+}
+
+int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, float* out_centers, float* out_D,
+              int64_t* out_idx, const void* Xq, const int8_t* Xq_exp, int32_t dtype, const kmpp_seed_opts* opts,
+              void* workspace, size_t ws_bytes, void* stream_) {
+  if (!X || !out_centers || !workspace) return KMPP_E_INVALID;
+  if (N < 1 || K < 1 || K > N || N > INT32_MAX || d < 1 || d > KMPP_MAX_D) return KMPP_E_INVALID;
+  if (!valid_dtype(dtype)) return KMPP_E_INVALID;
+  if (!aligned(X, 16) || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  if (dtype != KMPP_F32) {
+    if (!Xq || !aligned(Xq, 16)) return KMPP_E_INVALID;
+    if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
+  }
+  const SeedLayout L = seed_layout(N, K);
+  if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
+  const SeedVariant* v = nullptr;
+  int rpt = 0, ntiles = 0;
+  const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles);
+  if (rc != KMPP_OK) return rc;
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+
+  SeedParams p;
+  p.xs = dtype == KMPP_F32 ? static_cast<const void*>(X) : Xq;
+  p.xexp = Xq_exp;
+  p.X = X;
+  p.centers = out_centers;
+  p.idx = out_idx ? out_idx : reinterpret_cast<int64_t*>(ws + L.idx);
+  p.D = out_D ? out_D : reinterpret_cast<float*>(ws + L.D);
+  p.tsum = reinterpret_cast<double*>(ws + L.tsum);
+  p.ctl = reinterpret_cast<Ctl*>(ws);
+  p.recheck = opts ? opts->out_recheck : nullptr;
+  p.N = N;
+  p.d = d;
+  p.K = K;
+  p.pass = 0;
+  p.rows_per_tile = rpt;
+  p.ntiles = ntiles;
+  p.inst = opts ? opts->instance : 0u;
+  p.seed = seed;
+  hipEvent_t* ev = opts ? static_cast<hipEvent_t*>(opts->step_events) : nullptr;
+
+  void* args[] = {&p};
+  if (hipLaunchKernel(seed_init_fn(), dim3(1), dim3(256), args, 0, stream) != hipSuccess) return KMPP_E_HIP;
+  if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return KMPP_E_HIP;
+  const size_t shmem = sizeof(float) * (size_t)d;
+  for (int m = 1; m <= K; ++m) {
+    p.pass = m;
+    if (hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream) != hipSuccess)
+      return KMPP_E_HIP;
+    if (ev && hipEventRecord(ev[m], stream) != hipSuccess) return KMPP_E_HIP;
+  }
+  return KMPP_OK;
+}
+
+int kmpp_quantize(const float* X, int64_t N, int32_t d, int32_t dtype, void* Xq, int8_t* Xq_exp, void* stream) {
+  if (!X || !Xq || N < 1 || d < 1 || d > KMPP_MAX_D) return KMPP_E_INVALID;
+  if (dtype != KMPP_BF16 && dtype != KMPP_FP8_E4M3) return KMPP_E_INVALID;
+  if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
+  if (!aligned(X, 16) || !aligned(Xq, 16)) return KMPP_E_INVALID;
+  return launch_quantize(X, N, d, dtype, Xq, Xq_exp, static_cast<hipStream_t>(stream));
+}
+
+size_t kmpp_assign_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype) {
+  if (N < 1 || K < 1 || d < 1 || d > KMPP_MAX_D || !valid_dtype(dtype)) return 0;
+  return assign_workspace(N, d, K, dtype);
+}
+
+int kmpp_assign(const void* X, const int8_t* X_exp, int32_t dtype, const float* C, int64_t N, int32_t d, int32_t K,
+                int32_t* out_labels, float* out_mind, void* workspace, size_t ws_bytes, void* stream) {
+  if (!X || !C || !out_labels || !workspace) return KMPP_E_INVALID;
+  if (N < 1 || K < 1 || N > INT32_MAX || d < 1 || d > KMPP_MAX_D || !valid_dtype(dtype)) return KMPP_E_INVALID;
+  if (dtype == KMPP_FP8_E4M3 && !X_exp) return KMPP_E_INVALID;
+  if (!aligned(X, 16) || !aligned(C, 16) || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  if (ws_bytes < assign_workspace(N, d, K, dtype)) return KMPP_E_WORKSPACE;
+  return launch_assign(X, X_exp, dtype, C, N, d, K, out_labels, out_mind, workspace, ws_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+size_t kmpp_batched_workspace_bytes(const kmpp_instance* inst, int32_t n_inst) {
+  if (!inst || n_inst < 1) return 0;
+  return batched_workspace(inst, n_inst);
+}
+
+int kmpp_seed_batched_prepare(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  if (!inst || n_inst < 1 || !workspace || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  return batched_prepare(inst, n_inst, seed, workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int kmpp_seed_batched_launch(void* workspace, void* stream) {
+  if (!workspace || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  return batched_launch(workspace, static_cast<hipStream_t>(stream));
+}
+
+int kmpp_seed_batched(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, void* workspace, size_t ws_bytes,
+                      void* stream) {
+  const int rc = kmpp_seed_batched_prepare(inst, n_inst, seed, workspace, ws_bytes, stream);
+  if (rc != KMPP_OK) return rc;
+  return kmpp_seed_batched_launch(workspace, stream);
+}
+
+int kmpp_status(const void* workspace, void* stream, int32_t* out) {
+  if (!workspace || !out) return KMPP_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(s) != hipSuccess) return KMPP_E_HIP;
+  if (hipMemcpy(out, workspace, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return KMPP_E_HIP;
+  return KMPP_OK;
+}
+
+struct kmpp_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int kmpp_graph_begin(void* stream) {
+  return hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal) == hipSuccess
+             ? KMPP_OK
+             : KMPP_E_HIP;
+}
+
+int kmpp_graph_end(void* stream, kmpp_graph* out) {
+  if (!out) return KMPP_E_INVALID;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || !g) return KMPP_E_HIP;
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return KMPP_E_HIP;
+  }
+  kmpp_graph h = static_cast<kmpp_graph>(malloc(sizeof(kmpp_graph_s)));
+  if (!h) {
+    hipGraphExecDestroy(e);
+    hipGraphDestroy(g);
+    return KMPP_E_INVALID;
+  }
+  h->graph = g;
+  h->exec = e;
+  *out = h;
+  return KMPP_OK;
+}
+
+int kmpp_graph_launch(kmpp_graph g, void* stream) {
+  if (!g) return KMPP_E_INVALID;
+  return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? KMPP_OK : KMPP_E_HIP;
+}
+
+int kmpp_graph_destroy(kmpp_graph g) {
+  if (!g) return KMPP_E_INVALID;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  free(g);
+  return KMPP_OK;
+}
+
+int kmpp_tune_load(const char* path) {
+  if (!path) return KMPP_E_INVALID;
+  FILE* f = fopen(path, "r");
+  if (!f) return KMPP_E_INVALID;
+  char line[256];
+  int n = 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  while (fgets(line, sizeof(line), f)) {
+    char kind[32];
+    int dt, d, nt, rpt;
+    if (sscanf(line, "%31s %d %d %d %d", kind, &dt, &d, &nt, &rpt) == 5 && strcmp(kind, "seed") == 0 &&
+        valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0) {
+      g_tune[{dt, d}] = {nt, rpt};
+      ++n;
+    }
+  }
+  fclose(f);
+  return n;
+}
+
+const char* kmpp_strerror(int code) {
+  switch (code) {
+    case KMPP_OK: return "ok";
+    case KMPP_W_DEGENERATE: return "sum of distances was zero at a draw (fewer distinct points than seeds)";
+    case KMPP_E_INVALID: return "invalid argument";
+    case KMPP_E_WORKSPACE: return "workspace too small";
+    case KMPP_E_HIP: return "HIP runtime error";
+    case KMPP_E_NONFINITE: return "non-finite sum of distances (NaN or Inf in the points)";
+    case KMPP_E_UNSUPPORTED: return "unsupported shape or format";
+    case KMPP_E_TIMEOUT: return "a device-side wait expired";
+    default: return "unknown status";
+  }
+}
+
+int kmpp_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// kmpp_impl.h -- host/device shared declarations of libkmpp (not part of the
+// public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "kmpp.h"
+
+namespace kmpp {
+
+struct Ctl;
+
+// Arguments of one seed-loop launch (init or pass).
+struct SeedParams {
+  const void* xs;        // rows read by the distance pass (FP32, BF16 or FP8)
+  const int8_t* xexp;    // FP8 row exponents or null
+  const float* X;        // FP32 rows: centres are copied from here
+  float* centers;        // [K, d]
+  int64_t* idx;          // [K]
+  float* D;              // [N]
+  double* tsum;          // [ntiles] FP64 tile sums of D
+  Ctl* ctl;              // status and arrival counter
+  float* recheck;        // [2K] or null
+  int64_t N;
+  int32_t d;
+  int32_t K;
+  int32_t pass;          // 1..K: pass m uses centre m-1 and (m < K) draws seed m
+  int32_t rows_per_tile;
+  int32_t ntiles;
+  uint32_t inst;
+  uint64_t seed;
+};
+
+// One compiled seed-pass kernel.
+struct SeedVariant {
+  int fmt;
+  int dexact;        // > 0: exactly this d with 16-byte (or 8-byte) chunks; < 0: any d <= -dexact
+  int cb, g, cpl, u;
+  bool full;
+  int nt;
+  int rows_per_iter; // rows one workgroup covers per loop iteration
+  const void* fn;
+};
+
+const std::vector<SeedVariant>& seed_variants();
+const void* seed_init_fn();
+
+// Maximum number of tiles of one pass; bounds the tile-sum scan of the draw
+// and the workspace.
+constexpr int64_t kMaxTiles = 8192;
+
+// Assignment
+struct AssignParams;
+int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C, int64_t N, int d, int K,
+                  int32_t* labels, float* mind, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t assign_workspace(int64_t N, int d, int K, int dtype);
+
+// Quantisers
+int launch_quantize(const float* X, int64_t N, int d, int dtype, void* Xq, int8_t* Xq_exp, hipStream_t stream);
+
+// Batched
+size_t batched_workspace(const kmpp_instance* inst, int n_inst);
+int batched_prepare(const kmpp_instance* inst, int n_inst, uint64_t seed, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+int batched_launch(void* ws, hipStream_t stream);
+
+}  // namespace kmpp

@@ -1,0 +1,88 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/kmpp.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kl():
+    import paper_1908_02136_amd as k
+    if not os.path.exists(k.LIB_PATH):
+        pytest.skip("libkmpp.so not built")
+    k.lib()
+    return k
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "kmpp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kmpp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(kl):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(kl.lib(), n), n
+    assert sorted(kl.SYMBOLS) == names
+
+
+def test_strerror_and_version(kl):
+    assert kl.kmpp_version() >= 100
+    for c in [0, 1, -1, -2, -3, -4, -5, -6]:
+        assert kl.strerror(c) and kl.strerror(c) != "unknown status"
+
+
+def test_workspace_sizes(kl):
+    L = kl.lib()
+    assert L.kmpp_seed_workspace_bytes(0, 4, 1, 0) == 0
+    assert L.kmpp_seed_workspace_bytes(10, 4, 11, 0) == 0
+    assert L.kmpp_seed_workspace_bytes(10, 5000, 1, 0) == 0
+    assert L.kmpp_seed_workspace_bytes(10, 4, 1, 7) == 0
+    a = L.kmpp_seed_workspace_bytes(1_000_000, 32, 256, 0)
+    assert a >= 256 + 4 * 1_000_000 + 8 * 256
+    assert a % 256 == 0
+
+
+def test_seed_argument_checks_need_no_gpu(kl):
+    L = kl.lib()
+    fake = ctypes.c_void_p(1 << 20)       # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(1 << 21)
+    # N < K
+    assert L.kmpp_seed(fake, 10, 2, 11, 0, fake, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
+    # d out of range
+    assert L.kmpp_seed(fake, 10, 0, 1, 0, fake, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
+    assert L.kmpp_seed(fake, 10, 5000, 1, 0, fake, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
+    # misaligned X
+    assert L.kmpp_seed(ctypes.c_void_p((1 << 20) + 4), 10, 2, 1, 0, fake, None, None, None, None, 0, None, ws,
+                       1 << 30, None) == -1
+    # precision form without quantised rows / exponents
+    assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 1, None, ws, 1 << 30, None) == -1
+    assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, fake, None, 2, None, ws, 1 << 30, None) == -1
+    # small workspace
+    assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 0, None, ws, 16, None) == -2
+    # null outputs
+    assert L.kmpp_seed(fake, 10, 2, 1, 0, None, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
+
+
+def test_other_argument_checks_need_no_gpu(kl):
+    L = kl.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.kmpp_quantize(fake, 10, 4, 0, fake, None, None) == -1          # F32 is not a storage target
+    assert L.kmpp_quantize(fake, 10, 4, 2, fake, None, None) == -1          # FP8 needs exponents
+    assert L.kmpp_assign(None, None, 0, fake, 10, 4, 3, fake, None, fake, 1 << 30, None) == -1
+    assert L.kmpp_assign(fake, None, 2, fake, 10, 4, 3, fake, None, fake, 1 << 30, None) == -1
+    assert L.kmpp_seed_batched(None, 3, 0, fake, 1 << 30, None) == -1
+    assert L.kmpp_status(None, None, None) == -1
+    assert L.kmpp_tune_load(b"/nonexistent/file") == -1
+
+
+def test_tune_file_parses(kl, tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text("seed 0 32 256 512\nseed 0 64 512 256\n# comment\nseed 9 1 256 1\nbogus\n")
+    assert kl.lib().kmpp_tune_load(str(p).encode()) == 2

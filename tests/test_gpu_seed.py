@@ -1,0 +1,132 @@
+"""GPU parity of the seed loop (paper, Section II, Algorithms 1-2) against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import kmpp_synth
+import oracle
+from gpu_util import check_seed_run, run_seed
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_02136_amd as k
+    k.lib()
+    return k
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_small_workload_full_parity(kl):
+    w = kmpp_synth.small()
+    _say("small workload N=10000 d=2 K=16")
+    X = w.X.cuda()
+    for seed in range(8):
+        idx, C, D, st = run_seed(kl, X, w.K, seed)
+        assert st == 0
+        check_seed_run(w.X.numpy(), w.K, seed, idx, C, D)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
+def test_integer_lattice_is_bit_exact(kl, d):
+    # integer coordinates in [-100, 100]: every distance is an integer < 2^24
+    # (exact in FP32) and every FP64 sum is exact, so seeds and D must match
+    # the oracle exactly
+    N, K = 50_000 + 17, 40
+    Xh = kmpp_synth.lattice(N, d, seed=d)
+    _say("lattice", N, d, K)
+    idx, C, D, st = run_seed(kl, Xh.cuda(), K, seed=3)
+    assert st == 0
+    check_seed_run(Xh.numpy(), K, 3, idx, C, D, exact=True)
+
+
+@pytest.mark.parametrize("d", [1, 3, 4, 5, 8, 16, 17, 32, 33, 64, 100, 127, 128, 256, 300, 512, 1000])
+def test_shapes_ragged_tiles(kl, d):
+    N = 70_001
+    K = 12
+    Xh = kmpp_synth.gaussian(N, d, seed=100 + d)
+    _say("gaussian", N, d, K)
+    idx, C, D, st = run_seed(kl, Xh.cuda(), K, seed=d)
+    assert st == 0
+    check_seed_run(Xh.numpy(), K, d, idx, C, D)
+
+
+@pytest.mark.parametrize("threads,rpt", [(256, 0), (512, 0), (256, 64), (512, 1024), (256, 5000)])
+def test_launch_shapes(kl, threads, rpt):
+    N, d, K = 123_457, 32, 20
+    Xh = kmpp_synth.gaussian(N, d, seed=5)
+    _say("launch", threads, rpt)
+    idx, C, D, st = run_seed(kl, Xh.cuda(), K, seed=1, threads=threads, rows_per_tile=rpt)
+    assert st == 0
+    check_seed_run(Xh.numpy(), K, 1, idx, C, D)
+
+
+def test_K1_and_K_equals_N(kl):
+    Xh = kmpp_synth.gaussian(300, 5, seed=6)
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 1, seed=9)
+    check_seed_run(Xh.numpy(), 1, 9, idx, C, D)
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 300, seed=9)
+    assert st == 0
+    assert sorted(idx.tolist()) == list(range(300))
+    assert np.all(D == 0.0)
+    check_seed_run(Xh.numpy(), 300, 9, idx, C, D)
+
+
+def test_N1(kl):
+    Xh = torch.tensor([[1.5, -2.0, 3.0]])
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 1, seed=0)
+    assert idx.tolist() == [0] and D.tolist() == [0.0]
+
+
+def test_degenerate_and_nonfinite_status(kl):
+    Xh = torch.ones((1000, 4))
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 5, seed=2)
+    assert st == kl.W_DEGENERATE
+    r = oracle.seed(Xh.numpy(), 5, seed=2)
+    assert r.status == oracle.W_DEGENERATE
+    assert idx.tolist() == r.idx.tolist()
+    Xn = kmpp_synth.gaussian(1000, 4, seed=3)
+    Xn[17, 2] = float("nan")
+    idx, C, D, st = run_seed(kl, Xn.cuda(), 5, seed=2)
+    assert st == kl.E_NONFINITE
+
+
+def test_determinism_and_instance_ids(kl):
+    Xh = kmpp_synth.gaussian(200_000, 16, seed=8)
+    X = Xh.cuda()
+    a = run_seed(kl, X, 64, seed=77)
+    b = run_seed(kl, X, 64, seed=77)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2].view(np.uint32), b[2].view(np.uint32))
+    c = run_seed(kl, X, 64, seed=77, instance=5)
+    check_seed_run(Xh.numpy(), 64, 77, c[0], c[1], c[2], inst=5)
+
+
+def test_plain_workload_full_size(kl):
+    """N=1,000,000, d=32, K=256 Gaussian mixture: every draw replayed."""
+    w = kmpp_synth.plain(device="cuda")
+    _say("plain workload full size")
+    idx, C, D, st = run_seed(kl, w.X, w.K, seed=0)
+    assert st == 0
+    r, differ = check_seed_run(w.X.cpu().numpy(), w.K, 0, idx, C, D)
+    _say("draws differing near a boundary:", differ)
+
+
+def test_argument_errors(kl):
+    X = torch.zeros((10, 4), device="cuda")
+    with pytest.raises(kl.KmppError) as e:
+        kl.kmpp_seed(X, 11)
+    assert e.value.code == kl.E_INVALID
+    with pytest.raises(kl.KmppError) as e:
+        kl.kmpp_seed(X, 3, ws=kl.workspace(64, "cuda"))
+    assert e.value.code == kl.E_WORKSPACE
+    Xm = torch.zeros(41, device="cuda")[1:].view(10, 4)      # 4-byte offset: misaligned
+    with pytest.raises(kl.KmppError) as e:
+        kl.kmpp_seed(Xm, 3)
+    assert e.value.code == kl.E_INVALID
