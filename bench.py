@@ -51,27 +51,27 @@ def time_events(fn, steps, stream):
 
 def seed_pass_roofline(kl, X, K, rows_bytes, reps=3):
     """Average duration of the seed-pass launches, from HIP events recorded
-    on the launch stream between consecutive passes."""
+    on the launch stream right before and right after every pass."""
     import ctypes
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
     hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
     hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
     hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    evs = (ctypes.c_void_p * (K + 1))()
-    for i in range(K + 1):
+    evs = (ctypes.c_void_p * (2 * K))()
+    for i in range(2 * K):
         h = ctypes.c_void_p()
         assert hip.hipEventCreate(ctypes.byref(h)) == 0
         evs[i] = h
     durs = []
     for _ in range(reps):
         kl.kmpp_seed(X, K, 0, step_events=ctypes.cast(evs, ctypes.c_void_p).value)
-        hip.hipEventSynchronize(evs[K])
-        for i in range(K):
+        hip.hipEventSynchronize(evs[2 * K - 1])
+        for m in range(K):
             ms = ctypes.c_float()
-            hip.hipEventElapsedTime(ctypes.byref(ms), evs[i], evs[i + 1])
+            hip.hipEventElapsedTime(ctypes.byref(ms), evs[2 * m], evs[2 * m + 1])
             durs.append(ms.value)
-    for i in range(K + 1):
+    for i in range(2 * K):
         hip.hipEventDestroy(evs[i])
     avg_ms = float(np.mean(durs))
     gbs = rows_bytes / (avg_ms * 1e-3) / 1e9

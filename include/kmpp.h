@@ -71,15 +71,15 @@ enum {
 /* Optional knobs of kmpp_seed (pass NULL for defaults). */
 typedef struct kmpp_seed_opts {
   uint32_t instance;    /* Philox instance id: counter word 1 (default 0) */
-  int32_t threads;      /* threads per workgroup of the seed pass: 0 (tuned), 256, 512 or 1024 */
+  int32_t threads;      /* threads per workgroup of the seed pass: 0 (tuned), 256 or 512 */
   int32_t rows_per_tile;/* rows per workgroup tile: 0 (tuned) or a positive count */
   int32_t reserved;
   float* out_recheck;   /* device [K*2] or NULL.  Precision forms: for each draw m >= 1,
                            [2m] = D of the drawn row from the quantised rows before it is
                            committed, [2m+1] = its FP32 nearest distance recomputed from the
                            original FP32 row against the previous seeds. */
-  void* step_events;    /* host array of K+1 hipEvent_t or NULL: recorded on `stream` before
-                           the first pass and after each of the K passes (profiling only) */
+  void* step_events;    /* host array of 2K hipEvent_t or NULL: [2m-2] and [2m-1] are recorded
+                           on `stream` right before and right after pass m (profiling only) */
 } kmpp_seed_opts;
 
 /*

@@ -146,13 +146,16 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
 
   void* args[] = {&p};
   if (hipLaunchKernel(seed_init_fn(), dim3(1), dim3(256), args, 0, stream) != hipSuccess) return KMPP_E_HIP;
-  if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return KMPP_E_HIP;
   const size_t shmem = sizeof(float) * (size_t)d;
   for (int m = 1; m <= K; ++m) {
     p.pass = m;
+    if (ev && hipEventRecord(ev[2 * (m - 1)], stream) != hipSuccess) return KMPP_E_HIP;
     if (hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream) != hipSuccess)
       return KMPP_E_HIP;
-    if (ev && hipEventRecord(ev[m], stream) != hipSuccess) return KMPP_E_HIP;
+    if (ev && hipEventRecord(ev[2 * (m - 1) + 1], stream) != hipSuccess) return KMPP_E_HIP;
+    if (m < K && hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
+                     hipSuccess)
+      return KMPP_E_HIP;
   }
   return KMPP_OK;
 }

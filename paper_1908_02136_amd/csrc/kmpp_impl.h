@@ -47,10 +47,12 @@ struct SeedVariant {
 
 const std::vector<SeedVariant>& seed_variants();
 const void* seed_init_fn();
+const void* seed_draw_fn();
+int seed_draw_threads();
 
 // Maximum number of tiles of one pass; bounds the tile-sum scan of the draw
 // and the workspace.
-constexpr int64_t kMaxTiles = 8192;
+constexpr int64_t kMaxTiles = 8192;  // = draw threads (256) x tile sums per thread (32)
 
 // Assignment
 struct AssignParams;

@@ -1,37 +1,28 @@
 // seed.hip -- the k-means++ seed loop (paper, Section II, Algorithms 1-2).
 //
-// One launch per seed pass.  Pass m (1..K) streams the point rows once,
-// updates every point's nearest squared distance D = min(D, ||x - c_{m-1}||^2)
-// and reduces D per workgroup tile into an FP64 tile sum.  For m < K the
-// last workgroup of the pass to arrive (an epoch-free arrival counter that
-// only grows during a run) draws seed m:
-//   t = u_m * sum(D) (FP64),  tile j = first tile whose inclusive FP64 prefix
-//   of tile sums exceeds t,  seed = first row of tile j whose inclusive FP64
-//   prefix exceeds t,
-// and copies that row (the original FP32 row) into out_centers[m], which
-// the next pass broadcasts from LDS.  Nothing returns to the host between
-// passes, and no workgroup ever waits on another, so the launch needs no
-// co-residency.
+// Two launches per seed.  The pass kernel m (1..K) streams the point rows
+// once, updates every point's nearest squared distance
+// D = min(D, ||x - c_{m-1}||^2) and reduces D per workgroup tile into an FP64
+// tile sum.  For m < K a one-workgroup draw kernel then takes seed m by
+// inverting the FP64 cumulative distribution of D (tile sums, then the
+// owning tile's rows) at t = u_m * sum(D).  The next pass reads that
+// original FP32 row, broadcasts it from LDS and stores it in out_centers[m].
+// Nothing returns to the host between seeds.
 //
 // Row streaming: a row of d elements is split into 16-byte chunks; a group
 // of G lanes covers one row (G*CPL chunks), so one wave-wide load reads 64/G
 // whole consecutive rows (1 KiB contiguous).  Each lane keeps the centre
 // slice of its chunks in registers and the row distance is reduced across
 // the G lanes with xor shuffles.  U loads per lane are issued before any is
-// consumed.  D is read and written once per row per pass with one coalesced
-// access per 64 rows.
+// consumed.  D is read and written once per row per pass, 64 rows per
+// coalesced access.
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 
 namespace kmpp {
 
-// Tile-sum slots hold this NaN pattern (signalling, never produced by
-// arithmetic) tagged with the pass number until the tile's sum arrives.
-__device__ __forceinline__ uint64_t slot_sentinel(int pass) { return 0x7FF4000000000000ull | (uint32_t)pass; }
-
 // ---------------------------------------------------------------- S1
-// First seed: i0 = min(floor(u_0 N), N-1); resets the run's counters and
-// arms the tile-sum slots for pass 1.
+// First seed: i0 = min(floor(u_0 N), N-1); resets the status word.
 __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
   __shared__ int64_t s_i0;
   if (threadIdx.x == 0) {
@@ -42,8 +33,6 @@ __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
     p.idx[0] = i0;
     s_i0 = i0;
   }
-  uint64_t* slots = reinterpret_cast<uint64_t*>(p.tsum);
-  for (int i = threadIdx.x; i < p.ntiles; i += blockDim.x) slots[i] = slot_sentinel(1);
   __syncthreads();
   const float* src = p.X + s_i0 * (int64_t)p.d;
   for (int j = threadIdx.x; j < p.d; j += blockDim.x) p.centers[j] = src[j];
@@ -149,50 +138,91 @@ struct Streamer {
 };
 
 // ---------------------------------------------------------------- S3-S5
-// Draw seed p.pass.  Runs in the last workgroup of the pass to arrive.
-//  1. read the FP64 tile sums (waiting out any slot still armed), scan them
-//     in a fixed order, t = u * total, pick the first tile whose inclusive
-//     prefix exceeds t;
-//  2. recompute that tile's new D with the pass's own arithmetic (whether a
-//     row's D in memory is already this pass's or still the previous one,
-//     min(D, delta) is this pass's value), one workgroup iteration at a time,
-//     scanning each chunk in FP64 until the prefix exceeds t;
-//  3. publish the index, copy the original FP32 row to out_centers, arm the
-//     slots for the next pass.
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
-__device__ __forceinline__ void draw_and_commit(const SeedParams& p, const Streamer<FMT, CB, G, CPL, U, FULL, NT>& st,
-                                                bool first, int64_t prev) {
-  using S = Streamer<FMT, CB, G, CPL, U, FULL, NT>;
-  constexpr int NW = NT / 64;
-  constexpr int CH = NW * S::R;  // rows per chunk: one iteration of every wave
-  __shared__ double sh[NW + 1];
-  __shared__ int64_t shi[NW];
-  __shared__ double s_lo;
-  __shared__ float shf[NW];
-  __shared__ float chunk[CH];
-  __shared__ int64_t s_seed;
-  const int tid = threadIdx.x;
-  const int G_t = p.ntiles;
-  const uint64_t armed = slot_sentinel(p.pass);
-  uint64_t* slots = reinterpret_cast<uint64_t*>(p.tsum);
+// Draw seed p.pass from the pass just finished, in one workgroup (the
+// kernel boundary makes every D and tile sum of the pass visible):
+//  1. each thread loads a contiguous block of at most kDrawPer FP64 tile
+//     sums (all loads in flight together); the blocks are exclusive-scanned
+//     in a fixed order; t = u * total;
+//  2. each thread walks its block in registers from its prefix; the first
+//     tile whose inclusive prefix exceeds t owns the draw;
+//  3. the owner tile's D values (at most kDrawRows per thread) are loaded,
+//     scanned the same way from the tile's prefix, and the first row whose
+//     inclusive prefix exceeds t is the seed;
+//  4. the index is written; the next pass copies the row into out_centers
+//     (every draw is followed by a pass).
+// If rounding leaves no prefix above t, the last row with D > 0 is taken.
+constexpr int kDrawNT = 256;
+constexpr int kDrawPer = 32;   // tile sums per thread: kMaxTiles <= kDrawNT * kDrawPer
+constexpr int kDrawRows = 16;  // D values per thread kept in registers
 
-  const int per = (G_t + NT - 1) / NT;
-  const int b0 = min(G_t, tid * per), b1 = min(G_t, b0 + per);
-  double part = 0.0;
-  bool late = false;
-  for (int i = b0; i < b1; ++i) {
-    uint64_t b = __hip_atomic_load(&slots[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int spin = 0; b == armed && spin < (1 << 22); ++spin) {
-      __builtin_amdgcn_s_sleep(2);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      b = __hip_atomic_load(&slots[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    late |= b == armed;
-    part += __longlong_as_double((long long)b);
+// Exclusive scan of one double per thread over kDrawNT threads with a
+// single barrier; fixed association order.  Returns (exclusive, total).
+__device__ __forceinline__ double2 draw_scan(double v, double* sh) {
+  constexpr int NW = kDrawNT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  if (late) raise_status(p.ctl, KMPP_E_TIMEOUT);
-  double T;
-  const double ex = block_exclusive_scan<NT>(part, sh, &T);
+  double ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = 0.0;
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  double off = 0.0, tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w == wave) off = tot;
+    tot += sh[w];
+  }
+  __syncthreads();
+  return make_double2(off + ex, tot);
+}
+
+// (min a, max b) over the workgroup with one barrier.
+__device__ __forceinline__ int2 draw_minmax(int a, int b, int2* sh) {
+  constexpr int NW = kDrawNT / 64;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a = min(a, __shfl_xor(a, o, 64));
+    b = max(b, __shfl_xor(b, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = make_int2(a, b);
+  __syncthreads();
+  int2 r = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = make_int2(min(r.x, sh[w].x), max(r.y, sh[w].y));
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
+  constexpr int NT = kDrawNT;
+  constexpr int NW = NT / 64;
+  __shared__ double sh[NW];
+  __shared__ int2 shm[NW];
+  __shared__ float shf[NW];
+  __shared__ double s_lo;
+  const int tid = threadIdx.x;
+  const int G = p.ntiles;
+  const int NONE = INT_MAX;
+
+  const int per = (G + NT - 1) / NT;  // <= kDrawPer
+  const int b0 = min(G, tid * per);
+  const int nb = max(0, min(per, G - b0));
+  double v[kDrawPer];
+#pragma unroll
+  for (int k = 0; k < kDrawPer; ++k) v[k] = k < nb ? p.tsum[b0 + k] : 0.0;
+  double part = 0.0;
+  int lastpos = -1;
+#pragma unroll
+  for (int k = 0; k < kDrawPer; ++k) {
+    part += v[k];
+    if (v[k] > 0.0) lastpos = b0 + k;
+  }
+  const double2 sc = draw_scan(part, sh);
+  const double T = sc.y;
   const double u = draw_uniform(p.seed, (uint32_t)p.pass, p.inst);
 
   int64_t seed_row;
@@ -204,76 +234,73 @@ __device__ __forceinline__ void draw_and_commit(const SeedParams& p, const Strea
     seed_row = uniform_index(u, p.N);
   } else {
     const double t = __dmul_rn(u, T);
-    int64_t cand = INT64_MAX;
-    double run = ex;
-    int64_t lastpos = -1;
-    for (int i = b0; i < b1; ++i) {
-      const double v = __longlong_as_double((long long)slots[i]);
-      if (v > 0.0) lastpos = i;
-      const double nr = run + v;
-      if (cand == INT64_MAX && nr > t) cand = i;
-      if (cand == INT64_MAX) run = nr;
-    }
-    const int64_t tj = block_min<NT>(cand, shi);
-    if (cand == tj && cand != INT64_MAX) s_lo = run;
-    const int64_t tl = block_max<NT>(lastpos, shi);
-    int64_t tile = tj != INT64_MAX ? tj : tl;
-    if (tile < 0 || tile >= G_t) tile = G_t - 1;
-    __syncthreads();
-    const bool inside = tj != INT64_MAX;  // else: rounding put t past the total
-    double run2 = inside ? s_lo : 0.0;
-    const int64_t r0 = tile * (int64_t)p.rows_per_tile;
-    const int64_t r1 = min(p.N, r0 + (int64_t)p.rows_per_tile);
-    int64_t found = INT64_MAX, lastrow = -1;
-    for (int64_t c0 = r0; c0 < r1 && found == INT64_MAX; c0 += CH) {
-      const int64_t c1 = min(r1, c0 + (int64_t)CH);
-      st.iter(p, c0 + (int64_t)st.wave * S::R, c1, first, prev,
-              [&](int64_t row, float dn) { chunk[row - c0] = dn; });
-      __syncthreads();
-      const int n = (int)(c1 - c0);
-      const int per2 = (n + NT - 1) / NT;
-      const int q0 = min(n, tid * per2), q1 = min(n, q0 + per2);
-      double part2 = 0.0;
-      int64_t lp = -1;
-      for (int q = q0; q < q1; ++q) {
-        part2 += (double)chunk[q];
-        if (chunk[q] > 0.0f) lp = c0 + q;
+    int cand = NONE;
+    double run = sc.x, lo = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDrawPer; ++k) {
+      const double nr = run + v[k];
+      if (cand == NONE && k < nb && nr > t) {
+        cand = b0 + k;
+        lo = run;
       }
-      double tot2;
-      const double ex2 = block_exclusive_scan<NT>(part2, sh, &tot2);
-      int64_t c2 = INT64_MAX;
+      run = nr;
+    }
+    const int2 tm = draw_minmax(cand, lastpos, shm);
+    if (cand != NONE && cand == tm.x) s_lo = lo;
+    const bool inside = tm.x != NONE;  // else rounding put t at or past the total
+    int tile = inside ? tm.x : tm.y;
+    if (tile < 0 || tile >= G) tile = G - 1;
+    __syncthreads();
+    const double tlo = inside ? s_lo : 0.0;
+    const int64_t r0 = (int64_t)tile * p.rows_per_tile;
+    const int64_t r1 = min(p.N, r0 + (int64_t)p.rows_per_tile);
+    const int n = (int)(r1 - r0);
+    const int per2 = (n + NT - 1) / NT;
+    const int64_t q0 = r0 + min(n, tid * per2);
+    const int nq = max(0, min(per2, (int)(r1 - q0)));
+    int found = NONE, lastrow = -1;
+    if (per2 <= kDrawRows) {
+      float dv[kDrawRows];
+#pragma unroll
+      for (int k = 0; k < kDrawRows; ++k) dv[k] = k < nq ? p.D[q0 + k] : 0.0f;
+      double part2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kDrawRows; ++k) {
+        part2 += (double)dv[k];
+        if (dv[k] > 0.0f) lastrow = (int)(q0 - r0) + k;
+      }
+      const double2 sc2 = draw_scan(part2, sh);
       if (inside) {
-        double r = run2 + ex2;
-        for (int q = q0; q < q1; ++q) {
-          r += (double)chunk[q];
-          if (r > t) {
-            c2 = c0 + q;
-            break;
-          }
+        double r = tlo + sc2.x;
+#pragma unroll
+        for (int k = 0; k < kDrawRows; ++k) {
+          r += (double)dv[k];
+          if (found == NONE && k < nq && r > t) found = (int)(q0 - r0) + k;
         }
       }
-      found = block_min<NT>(c2, shi);
-      const int64_t lpc = block_max<NT>(lp, shi);
-      lastrow = lpc >= 0 ? lpc : lastrow;
-      run2 += tot2;
+    } else {  // very large tiles: same steps, values reloaded
+      double part2 = 0.0;
+      for (int k = 0; k < nq; ++k) {
+        const float dk = p.D[q0 + k];
+        part2 += (double)dk;
+        if (dk > 0.0f) lastrow = (int)(q0 - r0) + k;
+      }
+      const double2 sc2 = draw_scan(part2, sh);
+      if (inside) {
+        double r = tlo + sc2.x;
+        for (int k = 0; k < nq && found == NONE; ++k) {
+          r += (double)p.D[q0 + k];
+          if (r > t) found = (int)(q0 - r0) + k;
+        }
+      }
     }
-    seed_row = found != INT64_MAX ? found : (lastrow >= 0 ? lastrow : r1 - 1);
+    const int2 fm = draw_minmax(found, lastrow, shm);
+    seed_row = r0 + (fm.x != NONE ? fm.x : (fm.y >= 0 ? fm.y : n - 1));
   }
-  if (tid == 0) s_seed = seed_row;
-  __syncthreads();
-  seed_row = s_seed;
 
-  // precision forms: the drawn row's D from the quantised rows (recomputed
-  // with the pass's arithmetic) and its FP32 nearest distance from the
-  // original row against the earlier seeds
+  // precision forms: the drawn row's D from the quantised rows, and its FP32
+  // nearest distance recomputed from the original row against earlier seeds
   if (p.recheck != nullptr) {
-    const int64_t r0s = seed_row / p.rows_per_tile * (int64_t)p.rows_per_tile;
-    const int64_t r1s = min(p.N, r0s + (int64_t)p.rows_per_tile);
-    const int64_t c0 = r0s + (seed_row - r0s) / CH * CH;
-    const int64_t c1 = min(r1s, c0 + (int64_t)CH);
-    __syncthreads();
-    st.iter(p, c0 + (int64_t)st.wave * S::R, c1, first, prev,
-            [&](int64_t row, float dn) { chunk[row - c0] = dn; });
     const float* xr = p.X + seed_row * (int64_t)p.d;
     float best = INFINITY;
     for (int j = tid; j < p.pass; j += NT) {
@@ -285,28 +312,22 @@ __device__ __forceinline__ void draw_and_commit(const SeedParams& p, const Strea
       }
       best = fminf(best, a);
     }
-    best = block_minf<NT>(best, shf);  // (synchronises the chunk writes too)
+    best = block_minf<NT>(best, shf);
     if (tid == 0) {
-      p.recheck[2 * (int64_t)p.pass] = chunk[seed_row - c0];
+      p.recheck[2 * (int64_t)p.pass] = p.D[seed_row];
       p.recheck[2 * (int64_t)p.pass + 1] = best;
     }
   }
   if (tid == 0) p.idx[p.pass] = seed_row;
-  const float* src = p.X + seed_row * (int64_t)p.d;
-  float* dst = p.centers + (int64_t)p.pass * p.d;
-  for (int j = tid; j < p.d; j += NT) dst[j] = src[j];
-  const uint64_t next = slot_sentinel(p.pass + 1);
-  for (int i = tid; i < G_t; i += NT) slots[i] = next;
 }
 
-// ---------------------------------------------------------------- S2 (+S3-S5)
+// ---------------------------------------------------------------- S2
 template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   using S = Streamer<FMT, CB, G, CPL, U, FULL, NT>;
   constexpr int NW = NT / 64;
   extern __shared__ float cs[];  // centre row, d floats
   __shared__ double red[NW];
-  __shared__ int s_last;
 
   const int tid = threadIdx.x;
   const int d = p.d;
@@ -314,10 +335,14 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   const int64_t t0 = (int64_t)blockIdx.x * p.rows_per_tile;
   const int64_t t1 = min(p.N, t0 + (int64_t)p.rows_per_tile);
 
-  const float* cg = p.centers + (int64_t)(p.pass - 1) * d;
+  // centre c_{pass-1}: the original FP32 row of the previous seed
+  const int64_t cidx = p.idx[p.pass - 1];
+  const float* cg = p.X + cidx * (int64_t)d;
   for (int j = tid; j < d; j += NT) cs[j] = cg[j];
-  const int64_t prev = (FMT != FMT_F32) ? p.idx[p.pass - 1] : -1;
+  const int64_t prev = (FMT != FMT_F32) ? cidx : -1;
   __syncthreads();
+  if (blockIdx.x == 0 && p.pass > 1)
+    for (int j = tid; j < d; j += NT) p.centers[(int64_t)(p.pass - 1) * d + j] = cs[j];
   S st;
   st.init(cs, d);
 
@@ -332,20 +357,12 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   acc = wave_sum(acc);
   if ((tid & 63) == 0) red[st.wave] = acc;
   __syncthreads();
-  if (p.pass == p.K) return;  // final pass: D is the output, no draw
   if (tid == 0) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) s += red[w];
-    uint64_t* slots = reinterpret_cast<uint64_t*>(p.tsum);
-    __hip_atomic_store(&slots[blockIdx.x], (uint64_t)__double_as_longlong(s), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t old = __hip_atomic_fetch_add(&p.ctl->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = old == (uint32_t)p.pass * (uint32_t)p.ntiles - 1u;
+    p.tsum[blockIdx.x] = s;
   }
-  __syncthreads();
-  if (!s_last) return;
-  draw_and_commit<FMT, CB, G, CPL, U, FULL, NT>(p, st, first, prev);
 }
 
 // ---------------------------------------------------------------- registry
@@ -403,5 +420,7 @@ const std::vector<SeedVariant>& seed_variants() {
 }
 
 const void* seed_init_fn() { return reinterpret_cast<const void*>(&seed_init_kernel); }
+const void* seed_draw_fn() { return reinterpret_cast<const void*>(&seed_draw_kernel); }
+int seed_draw_threads() { return kDrawNT; }
 
 }  // namespace kmpp
