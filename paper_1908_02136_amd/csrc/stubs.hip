@@ -3,11 +3,6 @@
 #include "kmpp_impl.h"
 
 namespace kmpp {
-size_t assign_workspace(int64_t, int, int, int) { return 256; }
-int launch_assign(const void*, const int8_t*, int, const float*, int64_t, int, int, int32_t*, float*, void*, size_t,
-                  hipStream_t) {
-  return KMPP_E_UNSUPPORTED;
-}
 size_t batched_workspace(const kmpp_instance*, int) { return 256; }
 int batched_prepare(const kmpp_instance*, int, uint64_t, void*, size_t, hipStream_t) { return KMPP_E_UNSUPPORTED; }
 int batched_launch(void*, hipStream_t) { return KMPP_E_UNSUPPORTED; }
