@@ -185,7 +185,9 @@ int kmpp_graph_launch(kmpp_graph g, void* stream);
 int kmpp_graph_destroy(kmpp_graph g);
 
 /* Tuning table: text lines "seed <dtype> <d> <threads> <rows_per_tile>"
- * override the built-in choices for the seed pass.  Returns the number of
+ * override the built-in choices for the seed pass; lines
+ * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
+ * alpha) set the batched planner's cost model.  Returns the number of
  * entries read or KMPP_E_INVALID. */
 int kmpp_tune_load(const char* path);
 

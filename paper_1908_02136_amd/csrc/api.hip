@@ -268,11 +268,15 @@ int kmpp_tune_load(const char* path) {
   int n = 0;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   while (fgets(line, sizeof(line), f)) {
-    char kind[32];
+    char kind[32], key[32];
     int dt, d, nt, rpt;
+    double val;
     if (sscanf(line, "%31s %d %d %d %d", kind, &dt, &d, &nt, &rpt) == 5 && strcmp(kind, "seed") == 0 &&
         valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0) {
       g_tune[{dt, d}] = {nt, rpt};
+      ++n;
+    } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "batched") == 0 &&
+               batched_tune_set(key, val) == KMPP_OK) {
       ++n;
     }
   }

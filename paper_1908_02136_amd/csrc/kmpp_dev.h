@@ -68,6 +68,16 @@ __device__ __forceinline__ int64_t uniform_index(double u, int64_t N) {
   return i < N - 1 ? i : N - 1;
 }
 
+// Pointers into device memory as global-address-space pointers, so loads
+// through pointers read from memory (not kernel arguments) still compile to
+// global rather than flat instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
 // 2^e as a float for e in [-126, 127].
 __device__ __forceinline__ float exp2i(int e) { return __int_as_float((e + 127) << 23); }
 
@@ -84,6 +94,23 @@ template <>
 struct Raw<2> { using T = uint16_t; };
 template <>
 struct Raw<1> { using T = uint8_t; };
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// One CB-byte chunk through a global pointer.
+template <int CB>
+__device__ __forceinline__ typename Raw<CB>::T load_raw(gptr<const char> p) {
+  if constexpr (CB == 16) {
+    const v4u v = *(gptr<const v4u>)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else if constexpr (CB == 8) {
+    const v2u v = *(gptr<const v2u>)p;
+    return make_uint2(v.x, v.y);
+  } else {
+    return *(gptr<const typename Raw<CB>::T>)p;
+  }
+}
 
 template <int CB>
 __device__ __forceinline__ uint32_t raw_word(const typename Raw<CB>::T& r, int w) {

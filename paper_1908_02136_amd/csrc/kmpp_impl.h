@@ -68,5 +68,6 @@ size_t batched_workspace(const kmpp_instance* inst, int n_inst);
 int batched_prepare(const kmpp_instance* inst, int n_inst, uint64_t seed, void* ws, size_t ws_bytes,
                     hipStream_t stream);
 int batched_launch(void* ws, hipStream_t stream);
+int batched_tune_set(const char* key, double value);
 
 }  // namespace kmpp

@@ -18,6 +18,7 @@
 // coalesced access.
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
+#include "stream.h"
 
 namespace kmpp {
 
@@ -37,105 +38,6 @@ __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
   const float* src = p.X + s_i0 * (int64_t)p.d;
   for (int j = threadIdx.x; j < p.d; j += blockDim.x) p.centers[j] = src[j];
 }
-
-// ---------------------------------------------------------------- S2 core
-// Streams rows [r0, r1) with the wave layout described above and hands
-// every row's new nearest distance to `sink(row, dnew)`.  The arithmetic of
-// a row's distance depends only on the template parameters, so any caller
-// with the same instance recomputes bit-identical values.
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
-struct Streamer {
-  static constexpr int EB = ElemBytes<FMT>::value;
-  static constexpr int VEC = CB / EB;
-  static constexpr int RPL = 64 / G;  // rows per wave-wide load
-  static constexpr int R = U * RPL;   // rows per wave iteration
-  static constexpr int NW = NT / 64;
-  static constexpr int NJ = (U + G - 1) / G;  // D rows per lane per iteration
-  using RawT = typename Raw<CB>::T;
-
-  float cen[CPL][VEC];
-  int sub, rg, wave;
-
-  __device__ __forceinline__ void init(const float* cs, int d) {
-    const int lane = threadIdx.x & 63;
-    wave = threadIdx.x >> 6;
-    sub = lane % G;
-    rg = lane / G;
-    const int nchunk = d / VEC;
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-      const int c = sub + G * k;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) cen[k][e] = (FULL || c < nchunk) ? cs[c * VEC + e] : 0.0f;
-    }
-  }
-
-  // One iteration: this wave's R rows starting at `base` (rows >= r1 skipped).
-  template <class Sink>
-  __device__ __forceinline__ void iter(const SeedParams& p, int64_t base, int64_t r1, bool first, int64_t prev,
-                                       Sink&& sink) const {
-    const int d = p.d;
-    const int nchunk = d / VEC;
-    const char* xb = static_cast<const char*>(p.xs);
-    const int64_t rb = (int64_t)d * EB;
-    float dold[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int uu = sub + G * j;
-      const int64_t row = base + (int64_t)uu * RPL + rg;
-      dold[j] = (!first && uu < U && row < r1) ? p.D[row] : INFINITY;
-    }
-    RawT raw[U][CPL];
-    float sc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int64_t row = base + u * RPL + rg;
-      row = row < r1 ? row : r1 - 1;  // in bounds; the value is discarded
-      const char* rp = xb + row * rb;
-#pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const int c = sub + G * k;
-        if (FULL || c < nchunk)
-          raw[u][k] = *reinterpret_cast<const RawT*>(rp + (int64_t)c * CB);
-        else
-          raw[u][k] = RawT{};
-      }
-      if constexpr (FMT == FMT_FP8) sc[u] = exp2i((int)p.xexp[row]);
-    }
-    float delta[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      float a = 0.0f;
-#pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        float v[VEC];
-        decode<FMT, CB>(raw[u][k], v);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const float df = (FMT == FMT_FP8) ? fmaf(v[e], sc[u], -cen[k][e]) : v[e] - cen[k][e];
-          a = fmaf(df, df, a);
-        }
-      }
-#pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      delta[u] = a;
-    }
-    // lane (rg, sub) owns rows base + uu*RPL + rg for uu = sub, sub+G, ...
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int uu = sub + G * j;
-      float dv = delta[0];
-#pragma unroll
-      for (int w = 1; w < U; ++w) dv = (w == uu) ? delta[w] : dv;
-      const int64_t row = base + (int64_t)uu * RPL + rg;
-      if (uu < U && row < r1) {
-        float dn = first ? dv : fminf(dold[j], dv);
-        if constexpr (FMT != FMT_F32) dn = (row == prev) ? 0.0f : dn;
-        sink(row, dn);
-      }
-    }
-  }
-};
 
 // ---------------------------------------------------------------- S3-S5
 // Draw seed p.pass from the pass just finished, in one workgroup (the

@@ -1,0 +1,114 @@
+// stream.h -- the row streamer shared by the seed pass and the batched
+// kernel: D = min(D, ||x - c||^2) over a range of rows.
+#pragma once
+
+#include "kmpp_dev.h"
+#include "kmpp_impl.h"
+
+namespace kmpp {
+
+// A row of d elements is split into chunks of CB bytes; a group of G lanes
+// covers one row (G*CPL chunks), so one wave-wide load reads 64/G whole
+// consecutive rows.  Each lane keeps the centre slice of its chunks in
+// registers, the row distance is reduced across the G lanes with xor
+// shuffles, and U loads per lane are issued before any is consumed.
+// iter() handles the R = U*64/G rows of one wave starting at `base` and
+// hands every row's new nearest distance to `sink(row, dnew)`; a row's
+// arithmetic depends only on the template parameters.
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
+struct Streamer {
+  static constexpr int EB = ElemBytes<FMT>::value;
+  static constexpr int VEC = CB / EB;
+  static constexpr int RPL = 64 / G;  // rows per wave-wide load
+  static constexpr int R = U * RPL;   // rows per wave iteration
+  static constexpr int NW = NT / 64;
+  static constexpr int NJ = (U + G - 1) / G;  // D rows per lane per iteration
+  using RawT = typename Raw<CB>::T;
+
+  float cen[CPL][VEC];
+  int sub, rg, wave;
+
+  __device__ __forceinline__ void init(const float* cs, int d) {
+    const int lane = threadIdx.x & 63;
+    wave = threadIdx.x >> 6;
+    sub = lane % G;
+    rg = lane / G;
+    const int nchunk = d / VEC;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int c = sub + G * k;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) cen[k][e] = (FULL || c < nchunk) ? cs[c * VEC + e] : 0.0f;
+    }
+  }
+
+  // One iteration: this wave's R rows starting at `base` (rows >= r1 skipped).
+  template <class Sink>
+  __device__ __forceinline__ void iter(const SeedParams& p, int64_t base, int64_t r1, bool first, int64_t prev,
+                                       Sink&& sink) const {
+    const int d = p.d;
+    const int nchunk = d / VEC;
+    const gptr<const char> xb = as_global(static_cast<const char*>(p.xs));
+    const gptr<const float> Dg = as_global(static_cast<const float*>(p.D));
+    const gptr<const int8_t> xe = as_global(p.xexp);
+    const int64_t rb = (int64_t)d * EB;
+    float dold[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int uu = sub + G * j;
+      const int64_t row = base + (int64_t)uu * RPL + rg;
+      dold[j] = (!first && uu < U && row < r1) ? Dg[row] : INFINITY;
+    }
+    RawT raw[U][CPL];
+    float sc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int64_t row = base + u * RPL + rg;
+      row = row < r1 ? row : r1 - 1;  // in bounds; the value is discarded
+      const gptr<const char> rp = xb + row * rb;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        const int c = sub + G * k;
+        if (FULL || c < nchunk)
+          raw[u][k] = load_raw<CB>(rp + (int64_t)c * CB);
+        else
+          raw[u][k] = RawT{};
+      }
+      if constexpr (FMT == FMT_FP8) sc[u] = exp2i((int)xe[row]);
+    }
+    float delta[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        float v[VEC];
+        decode<FMT, CB>(raw[u][k], v);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float df = (FMT == FMT_FP8) ? fmaf(v[e], sc[u], -cen[k][e]) : v[e] - cen[k][e];
+          a = fmaf(df, df, a);
+        }
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      delta[u] = a;
+    }
+    // lane (rg, sub) owns rows base + uu*RPL + rg for uu = sub, sub+G, ...
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int uu = sub + G * j;
+      float dv = delta[0];
+#pragma unroll
+      for (int w = 1; w < U; ++w) dv = (w == uu) ? delta[w] : dv;
+      const int64_t row = base + (int64_t)uu * RPL + rg;
+      if (uu < U && row < r1) {
+        float dn = first ? dv : fminf(dold[j], dv);
+        if constexpr (FMT != FMT_F32) dn = (row == prev) ? 0.0f : dn;
+        sink(row, dn);
+      }
+    }
+  }
+};
+
+}  // namespace kmpp
