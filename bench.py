@@ -1,25 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the k-means++ hot path on one MI355X.
 
-A step is one full k-means++ seeding run (K passes over the rows, K-1 draws)
-followed by the nearest-seed assignment, on the N=1,000,000, d=32, K=256
-Gaussian-mixture workload (synthetic, seeded; inputs resident in HBM before
-the timed region).  Prints ONE JSON line.
+A step is one full k-means++ run on the N=1,000,000, d=32, K=256
+Gaussian-mixture workload: the seed loop (K passes over the rows, K-1
+draws) followed by the nearest-seed assignment.  Inputs are synthetic,
+seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
 
-  value     point-seed distances per second over the whole step: N*K / t_step
-  roofline  the seed-pass kernel: algorithmic X bytes per launch (N*d*4) over
-            its average launch duration from HIP events on its stream
-  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
-            the same workload, in the same unit
+  value         point-seed distances per second over the whole step,
+                N*K / t_step
+  roofline      the seed-pass kernel: algorithmic row bytes per launch
+                (N*d*4) over its average launch duration, from HIP events
+                attached to every pass launch on its stream (start and stop
+                of the kernel itself; a second timed run of the same step)
+  cpu_baseline  the FP64 oracle on the host cores, the same step on the
+                same rows (repeated to about 10 s of CPU work), same unit
+  forms         the precision forms (BF16 / per-row FP8 rows) on the
+                4,194,304 x 128 (K=1024) and 16,777,216 x 64 (K=4096)
+                workloads, and the batched form (512 uneven instances in one
+                persistent launch) against 512 plain calls; --no-forms skips
+                them
 
-Extra keys carry the precision and batched forms when requested
-(--forms).  Only one GPU is used; --gpus above 1 exits with a message.
+Only one GPU is used; --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
-import math
 import os
 import sys
 import time
@@ -31,14 +38,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_events(fn, steps, stream):
-    """Run fn `steps` times between two events on `stream`; returns ms per call."""
+def time_events(fn, steps, stream=None):
+    """Run fn `steps` times between two events on the stream; ms per call."""
+    stream = torch.cuda.current_stream() if stream is None else stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -49,52 +58,175 @@ def time_events(fn, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def seed_pass_roofline(kl, X, K, rows_bytes, reps=3):
-    """Average duration of the seed-pass launches, from HIP events recorded
-    on the launch stream right before and right after every pass."""
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
-    hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
-    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
-    hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
-    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    evs = (ctypes.c_void_p * (2 * K))()
-    for i in range(2 * K):
-        h = ctypes.c_void_p()
-        assert hip.hipEventCreate(ctypes.byref(h)) == 0
-        evs[i] = h
+class PassEvents:
+    """2K HIP events for kmpp_seed's step_events option.  They are created
+    with hipEventDisableSystemFence: timing-only events that skip the
+    system-scope cache write-back an ordinary event record performs, which
+    would otherwise be charged to the bracketed kernel."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, K):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.K = K
+        self.evs = (ctypes.c_void_p * (2 * K))()
+        for i in range(2 * K):
+            h = ctypes.c_void_p()
+            assert self.hip.hipEventCreateWithFlags(ctypes.byref(h), self.DISABLE_SYSTEM_FENCE) == 0
+            self.evs[i] = h
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.evs, ctypes.c_void_p).value
+
+    def pass_ms(self):
+        self.hip.hipEventSynchronize(self.evs[2 * self.K - 1])
+        out = []
+        for m in range(self.K):
+            ms = ctypes.c_float()
+            self.hip.hipEventElapsedTime(ctypes.byref(ms), self.evs[2 * m], self.evs[2 * m + 1])
+            out.append(ms.value)
+        return out
+
+    def __del__(self):
+        for i in range(2 * self.K):
+            self.hip.hipEventDestroy(self.evs[i])
+
+
+def seed_pass_rate(kl, X, K, row_bytes, reps=2, **kw):
+    """Average seed-pass duration (ms) and algorithmic GB/s from per-pass events."""
+    ev = PassEvents(K)
     durs = []
     for _ in range(reps):
-        kl.kmpp_seed(X, K, 0, step_events=ctypes.cast(evs, ctypes.c_void_p).value)
-        hip.hipEventSynchronize(evs[2 * K - 1])
-        for m in range(K):
-            ms = ctypes.c_float()
-            hip.hipEventElapsedTime(ctypes.byref(ms), evs[2 * m], evs[2 * m + 1])
-            durs.append(ms.value)
-    for i in range(2 * K):
-        hip.hipEventDestroy(evs[i])
-    avg_ms = float(np.mean(durs))
-    gbs = rows_bytes / (avg_ms * 1e-3) / 1e9
-    return avg_ms, gbs
+        kl.kmpp_seed(X, K, 0, step_events=ev.ptr, **kw)
+        durs += ev.pass_ms()
+    avg = float(np.mean(durs))
+    return avg, row_bytes / (avg * 1e-3) / 1e9
 
 
-def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 20.0):
-    """The FP64 oracle on the host cores: seeding draws on the same rows,
-    K' <= K passes chosen so the run stays near the time budget."""
+def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 10.0, max_reps: int = 5):
+    """The FP64 oracle as it stands, on all host cores: the same step (full
+    seeding, K passes, then the assignment of every row to the oracle's own
+    seeds) on the same rows, repeated until about `budget_s` of CPU work;
+    value in the bench's unit, N*K per step-second."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     N = Xh.shape[0]
-    t0 = time.perf_counter()
-    oracle.seed(Xh, 4, seed=0, nthreads=cores)
-    t4 = time.perf_counter() - t0
-    per_pass = t4 / 4
-    Ks = int(max(4, min(K, budget_s / max(per_pass, 1e-9))))
-    t0 = time.perf_counter()
-    oracle.seed(Xh, Ks, seed=0, nthreads=cores)
-    ts = time.perf_counter() - t0
-    return {"value": N * Ks / ts, "unit": "point-seed dists/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle seeding of the same {N}x{Xh.shape[1]} rows, first {Ks} of {K} passes "
-                      f"({ts:.1f} s)"}
+    times, ts_seed, ts_assign = [], [], []
+    while len(times) < max_reps and sum(times) < budget_s:
+        t0 = time.perf_counter()
+        r = oracle.seed(Xh, K, seed=0, nthreads=cores)
+        t1 = time.perf_counter()
+        oracle.assign(Xh, Xh[r.idx], nthreads=cores)
+        t2 = time.perf_counter()
+        ts_seed.append(t1 - t0)
+        ts_assign.append(t2 - t1)
+        times.append(t2 - t0)
+    t = float(np.mean(times))
+    return {"value": N * K / t, "unit": "point-seed dists/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole step on the same {N}x{Xh.shape[1]} rows (FP64 seeding, {K} passes: "
+                      f"{np.mean(ts_seed):.2f} s; FP64 assignment of all rows: {np.mean(ts_assign):.2f} s), "
+                      f"{len(times)} repetitions, {cores} threads"}
+
+
+def precision_forms(kl, name, w, reps):
+    """FP32 vs BF16 (vs FP8) seeding and assignment on one workload."""
+    X, N, d, K = w.X, w.N, w.d, w.K
+    res = {"workload": f"{name} N={N} d={d} K={K}"}
+    forms = [("f32", kl.KMPP_F32)] + [("bf16", kl.KMPP_BF16)] + ([("fp8", kl.KMPP_FP8_E4M3)] if d <= 128 else [])
+    phi = {}
+    for tag, dt in forms:
+        if dt == kl.KMPP_F32:
+            Xq = E = None
+            qms = 0.0
+        else:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Xq, E = kl.kmpp_quantize(X, dt)
+            torch.cuda.synchronize()
+            qms = (time.perf_counter() - t0) * 1e3
+        elem = {"f32": 4, "bf16": 2, "fp8": 1}[tag]
+        row_bytes = N * d * elem + (N if tag == "fp8" else 0)
+        rec = torch.zeros(2 * K, device="cuda")
+        out = {}
+
+        def run():
+            out["r"] = kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dt, out_recheck=rec if dt else None)
+
+        run()
+        torch.cuda.synchronize()
+        ms = time_events(run, reps)
+        idx, C, D, ws = out["r"]
+        st = kl.kmpp_status(ws)
+        pms, pgbs = seed_pass_rate(kl, X, K, row_bytes, reps=1, Xq=Xq, Xq_exp=E, dtype=dt)
+        Xa = X if dt == kl.KMPP_F32 else Xq
+        kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt)
+        torch.cuda.synchronize()
+        ams = time_events(lambda: kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt), reps)
+        flops = 2.0 * N * K * d
+        # BF16 / FP8 rows take two products (centre high part and remainder)
+        executed = flops * (1 if dt == kl.KMPP_F32 else 2)
+        peak = MFMA_PEAK_TFLOPS["f32" if dt == kl.KMPP_F32 else "bf16"]
+        phi[tag] = float(D.double().sum().item())
+        entry = {"seed_ms": ms, "status": st, "dists_per_s": N * K / (ms * 1e-3),
+                 "seed_GBps": row_bytes * K / (ms * 1e-3) / 1e9,
+                 "pass_us": pms * 1e3, "pass_GBps": pgbs, "pass_frac_hbm": pgbs / HBM_PEAK_GBS,
+                 "assign_ms": ams, "assign_TFLOPs": flops / (ams * 1e-3) / 1e12,
+                 "assign_frac_mfma": executed / (ams * 1e-3) / 1e12 / peak, "quantize_ms": qms,
+                 "phi": phi[tag]}
+        if dt:
+            r = rec.view(K, 2)[1:].double()
+            ratio = (r[:, 0] / r[:, 1].clamp_min(1e-30)).cpu().numpy()
+            entry["recheck_ratio_median"] = float(np.median(ratio))
+            entry["recheck_ratio_p99"] = float(np.quantile(np.abs(ratio - 1), 0.99))
+            entry["phi_vs_f32"] = phi[tag] / phi["f32"]
+        res[tag] = entry
+        _log(f"  {name} {tag}: seed {ms:.1f} ms ({entry['dists_per_s']:.3g} dists/s), pass {pms*1e3:.1f} us "
+             f"{pgbs:.0f} GB/s, assign {ams:.2f} ms {entry['assign_TFLOPs']:.1f} TF/s, status {st}")
+        del Xq, E, out, C, D
+        torch.cuda.empty_cache()
+    return res
+
+
+def batched_form(kl, reps):
+    import kmpp_synth
+    spec = kmpp_synth.batched_spec()
+    Xs = [kmpp_synth.batched_instance(b, spec.N[b], spec.d[b], spec.K[b], device="cuda") for b in range(512)]
+    outs, ws = kl.kmpp_seed_batched_prepare(Xs, spec.K, 0)
+    g = kl.Graph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with g.capture():
+            kl.kmpp_seed_batched_launch(ws)
+    g.launch(s)
+    s.synchronize()
+    ms = time_events(lambda: g.launch(s), reps, stream=s)
+    st = kl.kmpp_status(ws, stream=s)
+    # the same 512 instances as plain calls
+    pouts = [(torch.empty((K, X.shape[1]), device="cuda"), torch.empty(X.shape[0], device="cuda"),
+              torch.empty(K, dtype=torch.int64, device="cuda")) for X, K in zip(Xs, spec.K)]
+    pws = [kl.workspace(kl.kmpp_seed_workspace_bytes(X.shape[0], X.shape[1], K), "cuda")
+           for X, K in zip(Xs, spec.K)]
+
+    def plain():
+        for b, (X, K) in enumerate(zip(Xs, spec.K)):
+            C, D, I = pouts[b]
+            kl.kmpp_seed(X, K, 0, out_centers=C, out_D=D, out_idx=I, instance=b, ws=pws[b])
+
+    plain()
+    torch.cuda.synchronize()
+    pms = time_events(plain, max(1, reps // 2))
+    nk = sum(n * k for n, k in zip(spec.N, spec.K))
+    xb = sum(n * d * 4 * k for n, d, k in zip(spec.N, spec.d, spec.K))
+    _log(f"  batched: {ms:.2f} ms (status {st}), 512 plain calls {pms:.2f} ms")
+    return {"workload": "512 instances, N log-uniform [1e3,2e5], d in {8,16,64}, K uniform [8,256]",
+            "batched_ms": ms, "plain_calls_ms": pms, "speedup_vs_plain": pms / ms, "status": st,
+            "dists_per_s": nk / (ms * 1e-3), "GBps": xb / (ms * 1e-3) / 1e9,
+            "frac_hbm": xb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def main():
@@ -103,11 +235,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", action="store_true", help="also time the precision and batched forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched forms")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
+              "described in DESIGN.md, not built", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -117,7 +249,13 @@ def main():
     import paper_1908_02136_amd as kl
     kl.lib()
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+
+    # a plain device copy of known size (256 MiB read, 256 MiB written):
+    # the reference that scales the HBM byte counters of a profiled run
+    cal = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    cal_dst = torch.empty_like(cal)
+    cal_dst.copy_(cal)
+    del cal, cal_dst
 
     w = kmpp_synth.plain(device="cuda")
     X, N, d, K = w.X, w.N, w.d, w.K
@@ -125,22 +263,35 @@ def main():
     out_idx = torch.empty(K, dtype=torch.int64, device="cuda")
     out_C = torch.empty((K, d), dtype=torch.float32, device="cuda")
     out_D = torch.empty(N, dtype=torch.float32, device="cuda")
+    lab = torch.empty(N, dtype=torch.int32, device="cuda")
+    mind = torch.empty(N, dtype=torch.float32, device="cuda")
     ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, K), "cuda")
+    wa = kl.workspace(kl.kmpp_assign_workspace_bytes(N, d, K), "cuda")
+
+    def seed():
+        kl.kmpp_seed(X, K, 0, out_centers=out_C, out_D=out_D, out_idx=out_idx, ws=ws)
+
+    def assign():
+        kl.kmpp_assign(X, out_C, out_labels=lab, out_mind=mind, ws=wa)
 
     def step():
-        kl.kmpp_seed(X, K, 0, out_centers=out_C, out_D=out_D, out_idx=out_idx, ws=ws)
+        seed()
+        assign()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ms = time_events(step, args.steps, stream)
+    ms = time_events(step, args.steps)
     torch.cuda.synchronize()
     status = kl.kmpp_status(ws)
-    _log(f"step {ms:.3f} ms  status {status}")
+    seed_ms = time_events(seed, max(2, args.steps // 2))
+    assign_ms = time_events(assign, max(2, args.steps // 2))
+    _log(f"step {ms:.3f} ms (seed {seed_ms:.3f}, assign {assign_ms:.3f})  status {status}")
 
-    rows_bytes = N * d * 4
-    pass_ms, pass_gbs = seed_pass_roofline(kl, X, K, rows_bytes)
+    row_bytes = N * d * 4
+    pass_ms, pass_gbs = seed_pass_rate(kl, X, K, row_bytes)
     _log(f"seed pass avg {pass_ms * 1e3:.1f} us  {pass_gbs:.0f} GB/s")
+    aflops = 2.0 * N * K * d
 
     res = {
         "metric": "k-means++ point-seed dists/s",
@@ -155,13 +306,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "gaussian-mixture N=1000000 d=32 K=256 (256 components, Dirichlet weights)",
-                   "N": N, "d": d, "K": K, "parallelism": "single-gpu"},
-        "seed_loop_GBps": rows_bytes * K / (ms * 1e-3) / 1e9,
+        "config": {"workload": "gaussian-mixture seeding + assignment, N=1000000 d=32 K=256 (256 components, "
+                               "Dirichlet weights), FP32", "N": N, "d": d, "K": K},
+        "seed_ms": seed_ms,
+        "assign_ms": assign_ms,
+        "seed_loop_GBps": row_bytes * K / (seed_ms * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": pass_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "seed_pass_kernel (F32, d=32)", "avg_launch_us": pass_ms * 1e3},
+                     "kernel": "seed_pass_kernel<F32, d=32>", "avg_launch_us": pass_ms * 1e3,
+                     "bytes_per_launch": row_bytes},
+        "assign_roofline": {"bound": "mfma", "achieved": aflops / (assign_ms * 1e-3) / 1e12,
+                            "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                            "frac": aflops / (assign_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"]},
     }
+    del ws, wa
+    if not args.no_forms:
+        reps = 2
+        forms = {}
+        for name, fn in [("unitsphere", kmpp_synth.unitsphere), ("large", kmpp_synth.large)]:
+            wf = fn(device="cuda")
+            forms[name] = precision_forms(kl, name, wf, reps)
+            del wf
+            torch.cuda.empty_cache()
+        forms["batched"] = batched_form(kl, reps=3)
+        res["forms"] = forms
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(X.cpu().numpy(), K)
     print(json.dumps(res), flush=True)

@@ -78,8 +78,8 @@ typedef struct kmpp_seed_opts {
                            [2m] = D of the drawn row from the quantised rows before it is
                            committed, [2m+1] = its FP32 nearest distance recomputed from the
                            original FP32 row against the previous seeds. */
-  void* step_events;    /* host array of 2K hipEvent_t or NULL: [2m-2] and [2m-1] are recorded
-                           on `stream` right before and right after pass m (profiling only) */
+  void* step_events;    /* host array of 2K hipEvent_t or NULL: [2m-2] and [2m-1] track the
+                           start and the stop of pass m's kernel (profiling only) */
 } kmpp_seed_opts;
 
 /*

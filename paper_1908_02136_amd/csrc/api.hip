@@ -8,6 +8,8 @@
 #include <mutex>
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 
@@ -149,10 +151,13 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
   const size_t shmem = sizeof(float) * (size_t)d;
   for (int m = 1; m <= K; ++m) {
     p.pass = m;
-    if (ev && hipEventRecord(ev[2 * (m - 1)], stream) != hipSuccess) return KMPP_E_HIP;
-    if (hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream) != hipSuccess)
-      return KMPP_E_HIP;
-    if (ev && hipEventRecord(ev[2 * (m - 1) + 1], stream) != hipSuccess) return KMPP_E_HIP;
+    // with step events, the events are attached to the dispatch itself and
+    // track the kernel's own start and stop
+    const hipError_t le =
+        ev ? hipExtLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream,
+                                ev[2 * (m - 1)], ev[2 * (m - 1) + 1], 0)
+           : hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream);
+    if (le != hipSuccess) return KMPP_E_HIP;
     if (m < K && hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
                      hipSuccess)
       return KMPP_E_HIP;
