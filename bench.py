@@ -108,6 +108,29 @@ def seed_pass_rate(kl, X, K, row_bytes, reps=2, **kw):
     return avg, row_bytes / (avg * 1e-3) / 1e9
 
 
+PMC_PROFILE = os.path.join(ROOT, "profiles", "seed_pass_f32_d32_gaussian1M_pmc.md")
+PMC_SOURCES = ["paper_1908_02136_amd/csrc/seed.hip", "paper_1908_02136_amd/csrc/stream.h",
+               "paper_1908_02136_amd/csrc/kmpp_dev.h", "paper_1908_02136_amd/tune_table.txt"]
+
+
+def profiled_traffic():
+    """HBM bytes per seed-pass launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None if
+    the kernel sources or schedules changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(PMC_PROFILE).read()
+        want = txt.split("source_sha256:")[1].split()[0]
+        traffic = float(txt.split("traffic_bytes_per_launch:")[1].split()[0])
+        h = hashlib.sha256()
+        for f in PMC_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, IndexError, ValueError):
+        return None
+    return traffic if h.hexdigest() == want else None
+
+
 def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 10.0, max_reps: int = 5):
     """The FP64 oracle as it stands, on all host cores: the same step (full
     seeding, K passes, then the assignment of every row to the oracle's own
@@ -312,7 +335,7 @@ def main():
         "assign_ms": assign_ms,
         "seed_loop_GBps": row_bytes * K / (seed_ms * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": pass_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": pass_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "seed_pass_kernel<F32, d=32>", "avg_launch_us": pass_ms * 1e3,
                      "bytes_per_launch": row_bytes},
         "assign_roofline": {"bound": "mfma", "achieved": aflops / (assign_ms * 1e-3) / 1e12,

@@ -85,6 +85,9 @@ def lib():
         L.kmo_fp8_row_exponent.restype = i32
         L.kmo_fp8_quantize_rows.argtypes = [P, i64, i32, P, P]
         L.kmo_fp8_dequantize_rows.argtypes = [P, P, i64, i32, P]
+        L.kmo_fp8_quantize_rows_fast.argtypes = [P, i64, i32, P, P, i32]
+        L.kmo_fp8_encode_bisect.argtypes = [ctypes.c_double]
+        L.kmo_fp8_encode_bisect.restype = ctypes.c_uint8
         _lib = L
     return _lib
 
@@ -223,6 +226,20 @@ def fp8_quantize_rows(X):
     q = np.zeros((N, d), dtype=np.uint8)
     e = np.zeros(N, dtype=np.int8)
     lib().kmo_fp8_quantize_rows(_ptr(X), N, d, _ptr(q), _ptr(e))
+    return q, e
+
+
+def fp8_encode_bisect(v: float) -> int:
+    return int(lib().kmo_fp8_encode_bisect(float(v)))
+
+
+def fp8_quantize_rows_fast(X, nthreads: int = 0):
+    """fp8_quantize_rows with the bisection encoder, rows in parallel."""
+    X = _f32(X)
+    N, d = X.shape
+    q = np.zeros((N, d), dtype=np.uint8)
+    e = np.zeros(N, dtype=np.int8)
+    lib().kmo_fp8_quantize_rows_fast(_ptr(X), N, d, _ptr(q), _ptr(e), nthreads)
     return q, e
 
 

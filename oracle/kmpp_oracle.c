@@ -356,6 +356,7 @@ uint16_t kmo_bf16_encode(float x) {
 float kmo_bf16_decode(uint16_t h) { return kmo_bits_to_float((uint32_t)h << 16); }
 
 void kmo_bf16_encode_n(const float* x, int64_t n, uint16_t* out) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) out[i] = kmo_bf16_encode(x[i]);
 }
 void kmo_bf16_decode_n(const uint16_t* h, int64_t n, float* out) {
@@ -396,6 +397,35 @@ uint8_t kmo_fp8_encode(double v) {
   return (uint8_t)(sign | best);
 }
 
+/* The same nearest-code rule by bisection over the ascending table of the
+ * 127 non-negative finite codes (code c has value fp8_decode(c), increasing
+ * in c): the two neighbours of |v| are compared, ties go to the even code.
+ * Used for large inputs; equal to kmo_fp8_encode everywhere (tested). */
+static double kmo_fp8_table[127];
+static int kmo_fp8_table_ready = 0;
+
+uint8_t kmo_fp8_encode_bisect(double v) {
+  if (!kmo_fp8_table_ready) {
+    for (int c = 0; c < 127; ++c) kmo_fp8_table[c] = kmo_fp8_decode((uint8_t)c);
+    kmo_fp8_table_ready = 1;
+  }
+  if (isnan(v)) return 0x7F;
+  const uint8_t sign = (v < 0 || (v == 0 && signbit(v))) ? 0x80 : 0x00;
+  const double a = fabs(v);
+  if (a >= kmo_fp8_table[126]) return (uint8_t)(sign | 126);
+  int lo = 0, hi = 126; /* table[lo] <= a < table[hi] */
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (kmo_fp8_table[mid] <= a)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const double elo = a - kmo_fp8_table[lo], ehi = kmo_fp8_table[hi] - a;
+  int c = elo < ehi ? lo : (ehi < elo ? hi : ((lo & 1) == 0 ? lo : hi));
+  return (uint8_t)(sign | c);
+}
+
 /* Per-row power-of-two scale: e_i = smallest integer e with
  * amax_i <= 448 * 2^e (e_i = 0 for an all-zero row), clamped to
  * [-117, 127]; q = E4M3(x / 2^e_i).
@@ -424,7 +454,22 @@ void kmo_fp8_quantize_rows(const float* X, int64_t N, int32_t d, uint8_t* q, int
   }
 }
 
+/* Same as kmo_fp8_quantize_rows with the bisection encoder, rows in
+ * parallel; for the full-size workloads. */
+void kmo_fp8_quantize_rows_fast(const float* X, int64_t N, int32_t d, uint8_t* q, int8_t* ex, int32_t nthreads) {
+  const int nt = kmo_threads(nthreads);
+  kmo_fp8_encode_bisect(0.0); /* fill the table before the parallel region */
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t e = kmo_fp8_row_exponent(X + i * (int64_t)d, d);
+    ex[i] = (int8_t)e;
+    for (int32_t j = 0; j < d; ++j)
+      q[i * (int64_t)d + j] = kmo_fp8_encode_bisect(ldexp((double)X[i * (int64_t)d + j], -e));
+  }
+}
+
 void kmo_fp8_dequantize_rows(const uint8_t* q, const int8_t* ex, int64_t N, int32_t d, float* out) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i)
     for (int32_t j = 0; j < d; ++j)
       out[i * (int64_t)d + j] = (float)ldexp(kmo_fp8_decode(q[i * (int64_t)d + j]), ex[i]);

@@ -114,3 +114,19 @@ def test_fp8_row_quantisation_roundtrip(oracle_lib):
         np.testing.assert_array_equal(Xh[i], (ref.double().numpy() * s).astype(np.float32))
     rel = np.abs(Xh - X) / np.abs(X).max(axis=1, keepdims=True)
     assert rel.max() <= 2.0 ** -4 + 1e-12           # half an ulp of a 3-bit mantissa, relative to amax
+
+
+def test_fp8_bisection_encoder_equals_definition(oracle_lib):
+    pos = np.array([oracle.fp8_decode(c) for c in range(127)])
+    mids = 0.5 * (pos[:-1] + pos[1:])
+    rng = np.random.default_rng(9)
+    v = np.concatenate([pos, mids, np.nextafter(mids, 0), np.nextafter(mids, 1000), rng.uniform(0, 500, 20000),
+                        rng.standard_normal(5000) * 1e-3, [448.0, 449.0, 1e9, 0.0]])
+    v = np.concatenate([v, -v])
+    for a in v:
+        assert oracle.fp8_encode_bisect(a) == oracle.fp8_encode(a), a
+    X = kmpp_synth.gaussian(300, 33, seed=4, scale=30.0).numpy()
+    q1, e1 = oracle.fp8_quantize_rows(X)
+    q2, e2 = oracle.fp8_quantize_rows_fast(X)
+    np.testing.assert_array_equal(q1, q2)
+    np.testing.assert_array_equal(e1, e2)
