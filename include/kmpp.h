@@ -73,7 +73,9 @@ typedef struct kmpp_seed_opts {
   uint32_t instance;    /* Philox instance id: counter word 1 (default 0) */
   int32_t threads;      /* threads per workgroup of the seed pass: 0 (tuned), 256 or 512 */
   int32_t rows_per_tile;/* rows per workgroup tile: 0 (tuned) or a positive count */
-  int32_t reserved;
+  int16_t loads_per_lane; /* 16-byte row loads in flight per lane: 0 (tuned), 8 or 16 */
+  int16_t nontemporal;  /* row loads: -1 (tuned; non-temporal when the rows exceed 256 MiB),
+                           0 cached, 1 non-temporal */
   float* out_recheck;   /* device [K*2] or NULL.  Precision forms: for each draw m >= 1,
                            [2m] = D of the drawn row from the quantised rows before it is
                            committed, [2m+1] = its FP32 nearest distance recomputed from the
@@ -184,7 +186,8 @@ int kmpp_graph_end(void* stream, kmpp_graph* out);
 int kmpp_graph_launch(kmpp_graph g, void* stream);
 int kmpp_graph_destroy(kmpp_graph g);
 
-/* Tuning table: text lines "seed <dtype> <d> <threads> <rows_per_tile>"
+/* Tuning table: text lines
+ * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <nontemporal>]"
  * override the built-in choices for the seed pass; lines
  * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
  * alpha) set the batched planner's cost model.  Returns the number of

@@ -42,7 +42,8 @@ class KmppError(RuntimeError):
 
 class SeedOpts(ctypes.Structure):
     _fields_ = [("instance", ctypes.c_uint32), ("threads", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("out_recheck", ctypes.c_void_p), ("step_events", ctypes.c_void_p)]
+                ("loads_per_lane", ctypes.c_int16), ("nontemporal", ctypes.c_int16),
+                ("out_recheck", ctypes.c_void_p), ("step_events", ctypes.c_void_p)]
 
 
 class Instance(ctypes.Structure):
@@ -141,7 +142,8 @@ def kmpp_seed_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> 
 
 def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D=None, out_idx=None, Xq=None,
               Xq_exp=None, dtype: int = KMPP_F32, instance: int = 0, threads: int = 0, rows_per_tile: int = 0,
-              out_recheck=None, step_events=None, ws=None, stream=None):
+              loads_per_lane: int = 0, nontemporal: int = -1, out_recheck=None, step_events=None, ws=None,
+              stream=None):
     """k-means++ seeding of the rows of X (FP32 [N, d]).  Returns
     (idx int64 [K], centers FP32 [K, d], D FP32 [N], workspace)."""
     _require_cuda(X, Xq, Xq_exp)
@@ -152,7 +154,7 @@ def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D
     out_idx = torch.empty(K, dtype=torch.int64, device=dev) if out_idx is None else out_idx
     if ws is None:
         ws = workspace(kmpp_seed_workspace_bytes(N, d, K, dtype), dev)
-    opts = SeedOpts(instance, threads, rows_per_tile, 0,
+    opts = SeedOpts(instance, threads, rows_per_tile, loads_per_lane, nontemporal,
                     None if out_recheck is None else out_recheck.data_ptr(), step_events)
     rc = lib().kmpp_seed(_ptr(X), N, d, K, seed, _ptr(out_centers), _ptr(out_D), _ptr(out_idx), _ptr(Xq),
                          _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))

@@ -22,18 +22,24 @@ inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_
 int elem_bytes(int dtype) { return dtype == KMPP_F32 ? 4 : dtype == KMPP_BF16 ? 2 : 1; }
 bool valid_dtype(int dtype) { return dtype == KMPP_F32 || dtype == KMPP_BF16 || dtype == KMPP_FP8_E4M3; }
 
-// ---- tuning table: (dtype, d) -> (threads, rows_per_tile)
+// ---- tuning table: (dtype, d) -> launch schedule
+struct SeedTune {
+  int threads, rpt, u, ntl;  // u, ntl: 0 / -1 = automatic
+};
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, std::pair<int, int>> g_tune;
+std::map<std::pair<int, int>, SeedTune> g_tune;
 
-bool tuned(int dtype, int d, int* threads, int* rpt) {
+bool tuned(int dtype, int d, SeedTune* t) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find({dtype, d});
   if (it == g_tune.end()) return false;
-  *threads = it->second.first;
-  *rpt = it->second.second;
+  *t = it->second;
   return true;
 }
+
+// Rows larger than the 256 MiB last-level cache are streamed with
+// non-temporal loads; smaller ones stay cached between passes.
+constexpr int64_t kCachedRowBytes = 256ll << 20;
 
 struct SeedLayout {
   size_t tsum, D, idx, total;
@@ -52,11 +58,13 @@ SeedLayout seed_layout(int64_t N, int K) {
   return L;
 }
 
-const SeedVariant* pick_seed_variant(int dtype, int d, int nt) {
+const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, bool ntl) {
   const auto& vs = seed_variants();
   const int eb = elem_bytes(dtype);
-  for (const auto& v : vs)
-    if (v.fmt == dtype && v.nt == nt && v.dexact == d && (d * eb) % v.cb == 0) return &v;
+  for (int uu : {u, 8})
+    for (const auto& v : vs)
+      if (v.fmt == dtype && v.nt == nt && v.dexact == d && (d * eb) % v.cb == 0 && v.u == uu && v.ntl == ntl)
+        return &v;
   const SeedVariant* best = nullptr;
   for (const auto& v : vs)
     if (v.fmt == dtype && v.nt == nt && v.dexact < 0 && -v.dexact >= d)
@@ -68,16 +76,21 @@ const SeedVariant* pick_seed_variant(int dtype, int d, int nt) {
 
 int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, const SeedVariant** var,
                      int* rpt_out, int* ntiles_out) {
-  int nt = 256, rpt = 0;
-  int tnt, trpt;
-  if (tuned(dtype, d, &tnt, &trpt)) {
-    nt = tnt;
-    rpt = trpt;
+  int nt = 256, rpt = 0, u = 8;
+  int ntl = (int64_t)N * d * elem_bytes(dtype) > kCachedRowBytes ? 1 : 0;
+  SeedTune t;
+  if (tuned(dtype, d, &t)) {
+    nt = t.threads;
+    rpt = t.rpt;
+    if (t.u > 0) u = t.u;
+    if (t.ntl >= 0) ntl = t.ntl;
   }
   if (opts && opts->threads) nt = opts->threads;
   if (opts && opts->rows_per_tile > 0) rpt = opts->rows_per_tile;
+  if (opts && opts->loads_per_lane > 0) u = opts->loads_per_lane;
+  if (opts && opts->nontemporal >= 0) ntl = opts->nontemporal ? 1 : 0;
   if (nt != 256 && nt != 512) return KMPP_E_UNSUPPORTED;
-  const SeedVariant* v = pick_seed_variant(dtype, d, nt);
+  const SeedVariant* v = pick_seed_variant(dtype, d, nt, u, ntl != 0);
   if (!v) return KMPP_E_UNSUPPORTED;
   const int64_t it = v->rows_per_iter;
   if (rpt <= 0) {
@@ -274,11 +287,12 @@ int kmpp_tune_load(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   while (fgets(line, sizeof(line), f)) {
     char kind[32], key[32];
-    int dt, d, nt, rpt;
+    int dt, d, nt, rpt, u = 0, ntl = -1;
     double val;
-    if (sscanf(line, "%31s %d %d %d %d", kind, &dt, &d, &nt, &rpt) == 5 && strcmp(kind, "seed") == 0 &&
-        valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0) {
-      g_tune[{dt, d}] = {nt, rpt};
+    const int got = sscanf(line, "%31s %d %d %d %d %d %d", kind, &dt, &d, &nt, &rpt, &u, &ntl);
+    if (got >= 5 && strcmp(kind, "seed") == 0 && valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0 &&
+        (u == 0 || u == 8 || u == 16) && ntl >= -1 && ntl <= 1) {
+      g_tune[{dt, d}] = SeedTune{nt, rpt, u, ntl};
       ++n;
     } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "batched") == 0 &&
                batched_tune_set(key, val) == KMPP_OK) {

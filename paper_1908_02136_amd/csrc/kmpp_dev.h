@@ -98,17 +98,19 @@ struct Raw<1> { using T = uint8_t; };
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
-// One CB-byte chunk through a global pointer.
-template <int CB>
+// One CB-byte chunk through a global pointer.  NTL: a non-temporal load
+// (streamed data read once per pass that does not fit the caches).
+template <int CB, bool NTL = false>
 __device__ __forceinline__ typename Raw<CB>::T load_raw(gptr<const char> p) {
   if constexpr (CB == 16) {
-    const v4u v = *(gptr<const v4u>)p;
+    const v4u v = NTL ? __builtin_nontemporal_load((gptr<const v4u>)p) : *(gptr<const v4u>)p;
     return make_uint4(v.x, v.y, v.z, v.w);
   } else if constexpr (CB == 8) {
-    const v2u v = *(gptr<const v2u>)p;
+    const v2u v = NTL ? __builtin_nontemporal_load((gptr<const v2u>)p) : *(gptr<const v2u>)p;
     return make_uint2(v.x, v.y);
   } else {
-    return *(gptr<const typename Raw<CB>::T>)p;
+    using T = typename Raw<CB>::T;
+    return NTL ? __builtin_nontemporal_load((gptr<const T>)p) : *(gptr<const T>)p;
   }
 }
 

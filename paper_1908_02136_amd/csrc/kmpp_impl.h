@@ -40,6 +40,7 @@ struct SeedVariant {
   int dexact;        // > 0: exactly this d with 16-byte (or 8-byte) chunks; < 0: any d <= -dexact
   int cb, g, cpl, u;
   bool full;
+  bool ntl;          // non-temporal row loads
   int nt;
   int rows_per_iter; // rows one workgroup covers per loop iteration
   const void* fn;

@@ -224,9 +224,9 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
 }
 
 // ---------------------------------------------------------------- S2
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL>
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
-  using S = Streamer<FMT, CB, G, CPL, U, FULL, NT>;
+  using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, NTL>;
   constexpr int NW = NT / 64;
   extern __shared__ float cs[];  // centre row, d floats
   __shared__ double red[NW];
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
 }
 
 // ---------------------------------------------------------------- registry
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL>
 static SeedVariant make_variant(int dexact) {
   SeedVariant v;
   v.fmt = FMT;
@@ -279,45 +279,55 @@ static SeedVariant make_variant(int dexact) {
   v.u = U;
   v.full = FULL;
   v.nt = NT;
+  v.ntl = NTL;
   v.rows_per_iter = (NT / 64) * U * (64 / G);
-  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT>);
+  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, NTL>);
   return v;
 }
 
-#define KMPP_VARIANTS_NT(NT)                                                                  \
-  /* FP32, 16-byte chunks: d = 4*G*CPL */                                                    \
-  make_variant<FMT_F32, 8, 1, 1, 8, true, NT>(2), make_variant<FMT_F32, 16, 1, 1, 8, true, NT>(4), \
-      make_variant<FMT_F32, 16, 2, 1, 8, true, NT>(8), make_variant<FMT_F32, 16, 4, 1, 8, true, NT>(16), \
-      make_variant<FMT_F32, 16, 8, 1, 8, true, NT>(32), make_variant<FMT_F32, 16, 16, 1, 8, true, NT>(64), \
-      make_variant<FMT_F32, 16, 32, 1, 8, true, NT>(128), make_variant<FMT_F32, 16, 64, 1, 8, true, NT>(256), \
-      make_variant<FMT_F32, 16, 64, 2, 4, true, NT>(512),                                    \
-      /* BF16, 16-byte chunks: d = 8*G*CPL */                                                \
-      make_variant<FMT_BF16, 16, 1, 1, 8, true, NT>(8), make_variant<FMT_BF16, 16, 2, 1, 8, true, NT>(16), \
-      make_variant<FMT_BF16, 16, 4, 1, 8, true, NT>(32), make_variant<FMT_BF16, 16, 8, 1, 8, true, NT>(64), \
-      make_variant<FMT_BF16, 16, 16, 1, 8, true, NT>(128), make_variant<FMT_BF16, 16, 32, 1, 8, true, NT>(256), \
-      /* FP8, 16-byte chunks: d = 16*G*CPL */                                                \
-      make_variant<FMT_FP8, 16, 1, 1, 8, true, NT>(16), make_variant<FMT_FP8, 16, 2, 1, 8, true, NT>(32), \
-      make_variant<FMT_FP8, 16, 4, 1, 8, true, NT>(64), make_variant<FMT_FP8, 16, 8, 1, 8, true, NT>(128), \
-      make_variant<FMT_FP8, 16, 16, 1, 8, true, NT>(256),                                    \
-      /* any d: one element per chunk, G = min(64, pow2 >= d) lanes per row */               \
-      make_variant<FMT_F32, 4, 1, 1, 8, false, NT>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT>(-2), \
-      make_variant<FMT_F32, 4, 4, 1, 8, false, NT>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT>(-8), \
-      make_variant<FMT_F32, 4, 16, 1, 8, false, NT>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT>(-32), \
-      make_variant<FMT_F32, 4, 64, 1, 8, false, NT>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT>(-256), \
-      make_variant<FMT_F32, 4, 64, 16, 2, false, NT>(-1024), make_variant<FMT_F32, 4, 64, 64, 1, false, NT>(-4096), \
-      make_variant<FMT_BF16, 2, 1, 1, 8, false, NT>(-1), make_variant<FMT_BF16, 2, 2, 1, 8, false, NT>(-2), \
-      make_variant<FMT_BF16, 2, 4, 1, 8, false, NT>(-4), make_variant<FMT_BF16, 2, 8, 1, 8, false, NT>(-8), \
-      make_variant<FMT_BF16, 2, 16, 1, 8, false, NT>(-16), make_variant<FMT_BF16, 2, 32, 1, 8, false, NT>(-32), \
-      make_variant<FMT_BF16, 2, 64, 1, 8, false, NT>(-64), make_variant<FMT_BF16, 2, 64, 4, 8, false, NT>(-256), \
-      make_variant<FMT_BF16, 2, 64, 16, 2, false, NT>(-1024), make_variant<FMT_BF16, 2, 64, 64, 1, false, NT>(-4096), \
-      make_variant<FMT_FP8, 1, 1, 1, 8, false, NT>(-1), make_variant<FMT_FP8, 1, 2, 1, 8, false, NT>(-2), \
-      make_variant<FMT_FP8, 1, 4, 1, 8, false, NT>(-4), make_variant<FMT_FP8, 1, 8, 1, 8, false, NT>(-8), \
-      make_variant<FMT_FP8, 1, 16, 1, 8, false, NT>(-16), make_variant<FMT_FP8, 1, 32, 1, 8, false, NT>(-32), \
-      make_variant<FMT_FP8, 1, 64, 1, 8, false, NT>(-64), make_variant<FMT_FP8, 1, 64, 4, 8, false, NT>(-256), \
-      make_variant<FMT_FP8, 1, 64, 16, 2, false, NT>(-1024), make_variant<FMT_FP8, 1, 64, 64, 1, false, NT>(-4096)
+// Rows in 16-byte (d = 2: 8-byte) chunks for exact widths, U = 8 loads per
+// lane; the widths of the named workloads also with U = 16.
+#define KMPP_EXACT(NT, L)                                                                                   \
+  make_variant<FMT_F32, 8, 1, 1, 8, true, NT, L>(2), make_variant<FMT_F32, 16, 1, 1, 8, true, NT, L>(4),      \
+      make_variant<FMT_F32, 16, 2, 1, 8, true, NT, L>(8), make_variant<FMT_F32, 16, 4, 1, 8, true, NT, L>(16), \
+      make_variant<FMT_F32, 16, 8, 1, 8, true, NT, L>(32), make_variant<FMT_F32, 16, 16, 1, 8, true, NT, L>(64), \
+      make_variant<FMT_F32, 16, 32, 1, 8, true, NT, L>(128), make_variant<FMT_F32, 16, 64, 1, 8, true, NT, L>(256), \
+      make_variant<FMT_F32, 16, 64, 2, 4, true, NT, L>(512),                                                \
+      make_variant<FMT_F32, 16, 8, 1, 16, true, NT, L>(32), make_variant<FMT_F32, 16, 16, 1, 16, true, NT, L>(64), \
+      make_variant<FMT_F32, 16, 32, 1, 16, true, NT, L>(128),                                               \
+      make_variant<FMT_BF16, 16, 1, 1, 8, true, NT, L>(8), make_variant<FMT_BF16, 16, 2, 1, 8, true, NT, L>(16), \
+      make_variant<FMT_BF16, 16, 4, 1, 8, true, NT, L>(32), make_variant<FMT_BF16, 16, 8, 1, 8, true, NT, L>(64), \
+      make_variant<FMT_BF16, 16, 16, 1, 8, true, NT, L>(128), make_variant<FMT_BF16, 16, 32, 1, 8, true, NT, L>(256), \
+      make_variant<FMT_BF16, 16, 8, 1, 16, true, NT, L>(64), make_variant<FMT_BF16, 16, 16, 1, 16, true, NT, L>(128), \
+      make_variant<FMT_FP8, 16, 1, 1, 8, true, NT, L>(16), make_variant<FMT_FP8, 16, 2, 1, 8, true, NT, L>(32), \
+      make_variant<FMT_FP8, 16, 4, 1, 8, true, NT, L>(64), make_variant<FMT_FP8, 16, 8, 1, 8, true, NT, L>(128), \
+      make_variant<FMT_FP8, 16, 16, 1, 8, true, NT, L>(256),                                                \
+      make_variant<FMT_FP8, 16, 4, 1, 16, true, NT, L>(64), make_variant<FMT_FP8, 16, 8, 1, 16, true, NT, L>(128)
+
+// Any d: one element per chunk, G = min(64, pow2 >= d) lanes per row.
+#define KMPP_GENERIC(NT)                                                                                    \
+  make_variant<FMT_F32, 4, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT, false>(-2), \
+      make_variant<FMT_F32, 4, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT, false>(-8), \
+      make_variant<FMT_F32, 4, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT, false>(-32), \
+      make_variant<FMT_F32, 4, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT, false>(-256), \
+      make_variant<FMT_F32, 4, 64, 16, 2, false, NT, false>(-1024),                                         \
+      make_variant<FMT_F32, 4, 64, 64, 1, false, NT, false>(-4096),                                         \
+      make_variant<FMT_BF16, 2, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_BF16, 2, 2, 1, 8, false, NT, false>(-2), \
+      make_variant<FMT_BF16, 2, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_BF16, 2, 8, 1, 8, false, NT, false>(-8), \
+      make_variant<FMT_BF16, 2, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_BF16, 2, 32, 1, 8, false, NT, false>(-32), \
+      make_variant<FMT_BF16, 2, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_BF16, 2, 64, 4, 8, false, NT, false>(-256), \
+      make_variant<FMT_BF16, 2, 64, 16, 2, false, NT, false>(-1024),                                        \
+      make_variant<FMT_BF16, 2, 64, 64, 1, false, NT, false>(-4096),                                        \
+      make_variant<FMT_FP8, 1, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_FP8, 1, 2, 1, 8, false, NT, false>(-2), \
+      make_variant<FMT_FP8, 1, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_FP8, 1, 8, 1, 8, false, NT, false>(-8), \
+      make_variant<FMT_FP8, 1, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_FP8, 1, 32, 1, 8, false, NT, false>(-32), \
+      make_variant<FMT_FP8, 1, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_FP8, 1, 64, 4, 8, false, NT, false>(-256), \
+      make_variant<FMT_FP8, 1, 64, 16, 2, false, NT, false>(-1024),                                         \
+      make_variant<FMT_FP8, 1, 64, 64, 1, false, NT, false>(-4096)
 
 const std::vector<SeedVariant>& seed_variants() {
-  static const std::vector<SeedVariant> v = {KMPP_VARIANTS_NT(256), KMPP_VARIANTS_NT(512)};
+  static const std::vector<SeedVariant> v = {KMPP_EXACT(256, false), KMPP_EXACT(256, true), KMPP_EXACT(512, false),
+                                             KMPP_EXACT(512, true), KMPP_GENERIC(256), KMPP_GENERIC(512)};
   return v;
 }
 

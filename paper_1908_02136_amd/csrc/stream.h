@@ -14,8 +14,9 @@ namespace kmpp {
 // shuffles, and U loads per lane are issued before any is consumed.
 // iter() handles the R = U*64/G rows of one wave starting at `base` and
 // hands every row's new nearest distance to `sink(row, dnew)`; a row's
-// arithmetic depends only on the template parameters.
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT>
+// arithmetic depends only on the template parameters.  NTL selects
+// non-temporal row loads for inputs larger than the last-level cache.
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL = false>
 struct Streamer {
   static constexpr int EB = ElemBytes<FMT>::value;
   static constexpr int VEC = CB / EB;
@@ -70,7 +71,7 @@ struct Streamer {
       for (int k = 0; k < CPL; ++k) {
         const int c = sub + G * k;
         if (FULL || c < nchunk)
-          raw[u][k] = load_raw<CB>(rp + (int64_t)c * CB);
+          raw[u][k] = load_raw<CB, NTL>(rp + (int64_t)c * CB);
         else
           raw[u][k] = RawT{};
       }

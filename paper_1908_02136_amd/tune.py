@@ -1,12 +1,14 @@
 """Autotuner for libkmpp's launch schedules (run on the GPU).
 
 * Seed pass: for each (storage format, d) it times whole seeding runs over a
-  grid of (threads per workgroup, rows per tile) and keeps the fastest;
+  grid of (threads per workgroup, rows per tile, row loads in flight per
+  lane, cached or non-temporal row loads) and keeps the fastest;
 * batched planner: it times the 512-instance batch over a grid of the
   cost-model knobs (workgroups per CU, the cap on one instance's time) and
   keeps the fastest.
 
-The result is written as text lines ``seed <dtype> <d> <threads> <rows>`` and
+The result is written as text lines
+``seed <dtype> <d> <threads> <rows> <loads per lane> <non-temporal>`` and
 ``batched <key> <value>`` to ``tune_table.txt`` next to the library, which
 the binding loads at import (``kmpp_tune_load``).
 
@@ -49,16 +51,19 @@ def tune_seed(kl, cases, quick):
         best = None
         for nt in (256, 512):
             for rpt in rpt_grid:
-                try:
-                    ms = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt,
-                                                    rows_per_tile=rpt))
-                except kl.KmppError:
-                    continue
-                print(f"seed dtype={dtype} d={d} N={N} K={K} threads={nt} rows={rpt}: {ms:.3f} ms", flush=True)
-                if best is None or ms < best[0]:
-                    best = (ms, nt, rpt)
+                for u in (8, 16):
+                    for ntl in (0, 1):
+                        try:
+                            ms = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt,
+                                                            rows_per_tile=rpt, loads_per_lane=u, nontemporal=ntl))
+                        except kl.KmppError:
+                            continue
+                        print(f"seed dtype={dtype} d={d} N={N} K={K} threads={nt} rows={rpt} u={u} nt={ntl}: "
+                              f"{ms:.3f} ms", flush=True)
+                        if best is None or ms < best[0]:
+                            best = (ms, nt, rpt, u, ntl)
         if best:
-            lines.append(f"seed {dtype} {d} {best[1]} {best[2]}")
+            lines.append(f"seed {dtype} {d} {best[1]} {best[2]} {best[3]} {best[4]}")
         del X, Xq, E
         torch.cuda.empty_cache()
     return lines
