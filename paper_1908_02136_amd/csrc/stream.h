@@ -29,11 +29,21 @@ struct Streamer {
   float cen[CPL][VEC];
   int sub, rg, wave;
 
-  __device__ __forceinline__ void init(const float* cs, int d) {
+  // The loaded state of one iteration: rows, FP8 row scales, old D.
+  struct Batch {
+    RawT raw[U][CPL];
+    float sc[U];
+    float dold[NJ];
+  };
+
+  __device__ __forceinline__ void layout() {
     const int lane = threadIdx.x & 63;
     wave = threadIdx.x >> 6;
     sub = lane % G;
     rg = lane / G;
+  }
+
+  __device__ __forceinline__ void set_centre(const float* cs, int d) {
     const int nchunk = d / VEC;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
@@ -43,25 +53,26 @@ struct Streamer {
     }
   }
 
-  // One iteration: this wave's R rows starting at `base` (rows >= r1 skipped).
-  template <class Sink>
-  __device__ __forceinline__ void iter(const SeedParams& p, int64_t base, int64_t r1, bool first, int64_t prev,
-                                       Sink&& sink) const {
+  __device__ __forceinline__ void init(const float* cs, int d) {
+    layout();
+    set_centre(cs, d);
+  }
+
+  // Issue the loads of this wave's R rows starting at `base` (rows >= r1
+  // are clamped in bounds and later discarded); needs no centre.
+  __device__ __forceinline__ void load(const SeedParams& p, int64_t base, int64_t r1, bool first, Batch& b) const {
     const int d = p.d;
     const int nchunk = d / VEC;
     const gptr<const char> xb = as_global(static_cast<const char*>(p.xs));
     const gptr<const float> Dg = as_global(static_cast<const float*>(p.D));
     const gptr<const int8_t> xe = as_global(p.xexp);
     const int64_t rb = (int64_t)d * EB;
-    float dold[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int uu = sub + G * j;
       const int64_t row = base + (int64_t)uu * RPL + rg;
-      dold[j] = (!first && uu < U && row < r1) ? Dg[row] : INFINITY;
+      b.dold[j] = (!first && uu < U && row < r1) ? Dg[row] : INFINITY;
     }
-    RawT raw[U][CPL];
-    float sc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       int64_t row = base + u * RPL + rg;
@@ -71,12 +82,18 @@ struct Streamer {
       for (int k = 0; k < CPL; ++k) {
         const int c = sub + G * k;
         if (FULL || c < nchunk)
-          raw[u][k] = load_raw<CB, NTL>(rp + (int64_t)c * CB);
+          b.raw[u][k] = load_raw<CB, NTL>(rp + (int64_t)c * CB);
         else
-          raw[u][k] = RawT{};
+          b.raw[u][k] = RawT{};
       }
-      if constexpr (FMT == FMT_FP8) sc[u] = exp2i((int)xe[row]);
+      if constexpr (FMT == FMT_FP8) b.sc[u] = exp2i((int)xe[row]);
     }
+  }
+
+  // Distances of a loaded batch to the centre, new D to `sink(row, dnew)`.
+  template <class Sink>
+  __device__ __forceinline__ void compute(int64_t base, int64_t r1, bool first, int64_t prev, const Batch& b,
+                                          Sink&& sink) const {
     float delta[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -84,10 +101,10 @@ struct Streamer {
 #pragma unroll
       for (int k = 0; k < CPL; ++k) {
         float v[VEC];
-        decode<FMT, CB>(raw[u][k], v);
+        decode<FMT, CB>(b.raw[u][k], v);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const float df = (FMT == FMT_FP8) ? fmaf(v[e], sc[u], -cen[k][e]) : v[e] - cen[k][e];
+          const float df = (FMT == FMT_FP8) ? fmaf(v[e], b.sc[u], -cen[k][e]) : v[e] - cen[k][e];
           a = fmaf(df, df, a);
         }
       }
@@ -104,11 +121,20 @@ struct Streamer {
       for (int w = 1; w < U; ++w) dv = (w == uu) ? delta[w] : dv;
       const int64_t row = base + (int64_t)uu * RPL + rg;
       if (uu < U && row < r1) {
-        float dn = first ? dv : fminf(dold[j], dv);
+        float dn = first ? dv : fminf(b.dold[j], dv);
         if constexpr (FMT != FMT_F32) dn = (row == prev) ? 0.0f : dn;
         sink(row, dn);
       }
     }
+  }
+
+  // One iteration: load, then compute.
+  template <class Sink>
+  __device__ __forceinline__ void iter(const SeedParams& p, int64_t base, int64_t r1, bool first, int64_t prev,
+                                       Sink&& sink) const {
+    Batch b;
+    load(p, base, r1, first, b);
+    compute(base, r1, first, prev, b, sink);
   }
 };
 
