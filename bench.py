@@ -19,6 +19,11 @@ seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
                 workloads, and the batched form (512 uneven instances in one
                 persistent launch) against 512 plain calls; --no-forms skips
                 them
+  memory_spaces the paper's memory-space comparison (Section II, Figs. 2c
+                and 3c) on this chip: every row path (cached, non-temporal,
+                buffer descriptor) x centre source (LDS, scalar, global) on
+                the paper's 2-D shapes and on 32- and 128-wide rows;
+                --no-spaces skips it
 
 Only one GPU is used; --gpus above 1 exits with a message.
 """
@@ -252,6 +257,47 @@ def batched_form(kl, reps):
             "frac_hbm": xb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def memory_spaces(kl, reps=3):
+    """The paper's memory-space experiment (Section II; Figs. 2c, 3c) on this
+    chip: every row path x centre source at one launch schedule, on the
+    paper's two-dimensional shapes and on 32- and 128-wide rows.  The paper's
+    three designs map to: global = cached rows + per-lane global centre,
+    constant = cached rows + scalar (constant-cache) centre, texture =
+    buffer-descriptor rows + global centre."""
+    import kmpp_synth
+    cases = [("paper_k", lambda: kmpp_synth.paper_shape("paper_k", device="cuda")),
+             ("paper_n", lambda: kmpp_synth.paper_shape("paper_n", device="cuda")),
+             ("plain", lambda: kmpp_synth.plain(device="cuda")),
+             ("unitsphere K=64", lambda: kmpp_synth.unitsphere(device="cuda", K=64))]
+    out = {}
+    for name, make in cases:
+        w = make()
+        X, N, d, K = w.X, w.N, w.d, w.K
+        row_bytes = N * d * 4
+        grid = {}
+        for rn, rl in kl.ROW_PATHS.items():
+            for cn, cs in kl.CENTRE_SOURCES.items():
+                kw = dict(threads=256, loads_per_lane=8, row_loads=rl, centre_source=cs)
+                kl.kmpp_seed(X, K, 0, **kw)
+                torch.cuda.synchronize()
+                ms = time_events(lambda: kl.kmpp_seed(X, K, 0, **kw), reps)
+                pms, gbs = seed_pass_rate(kl, X, K, row_bytes, reps=1, **kw)
+                grid[f"{rn}/{cn}"] = {"seed_ms": ms, "pass_us": pms * 1e3, "pass_GBps": gbs}
+        base = grid["cached/global"]["seed_ms"]
+        for v in grid.values():
+            v["speedup_vs_global"] = base / v["seed_ms"]
+        analog = {"global": "cached/global", "constant": "cached/scalar", "texture": "buffer/global"}
+        out[name] = {"workload": f"{name} N={N} d={d} K={K}", "grid": grid,
+                     "paper_designs": {k: {"combination": v, "speedup_vs_global": grid[v]["speedup_vs_global"]}
+                                       for k, v in analog.items()}}
+        best = min(grid, key=lambda k: grid[k]["seed_ms"])
+        _log(f"  memory spaces {name}: " + ", ".join(f"{k} {v['pass_us']:.1f} us" for k, v in grid.items())
+             + f"; best {best}")
+        del w, X
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +305,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched forms")
+    ap.add_argument("--no-spaces", action="store_true", help="skip the memory-space comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
@@ -353,6 +400,8 @@ def main():
             torch.cuda.empty_cache()
         forms["batched"] = batched_form(kl, reps=3)
         res["forms"] = forms
+    if not args.no_spaces:
+        res["memory_spaces"] = memory_spaces(kl)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(X.cpu().numpy(), K)
     print(json.dumps(res), flush=True)

@@ -68,20 +68,48 @@ enum {
 
 #define KMPP_MAX_D 4096
 
+/*
+ * Memory spaces of the seed pass (Section II keeps the points in global or
+ * texture memory and the centroids in global or constant memory; Figs. 2c
+ * and 3c compare them).  All choices give bit-identical results; they differ
+ * only in speed.  Non-default choices exist for FP32 rows with d in
+ * {2, 32, 64, 128} at 256 threads and 8 loads per lane (KMPP_E_UNSUPPORTED
+ * otherwise).
+ *
+ * Row paths (kmpp_seed_opts.row_loads):
+ *   KMPP_ROWS_CACHED       plain global loads, kept in the caches
+ *   KMPP_ROWS_NONTEMPORAL  non-temporal global loads (streamed once per pass)
+ *   KMPP_ROWS_BUFFER       loads through a bounds-checked buffer descriptor per
+ *                          workgroup tile (the descriptor-addressed read-only
+ *                          path, the analogue of a texture fetch); needs a tile
+ *                          of at most 2^31 bytes
+ * Centre sources (kmpp_seed_opts.centre_source):
+ *   KMPP_CENTRE_LDS        copied once per workgroup into LDS (the default)
+ *   KMPP_CENTRE_SCALAR     scalar loads into scalar registers through the
+ *                          scalar data cache (the constant-cache analogue)
+ *   KMPP_CENTRE_GLOBAL     vector loads by every lane from global memory
+ */
+enum { KMPP_ROWS_CACHED = 0, KMPP_ROWS_NONTEMPORAL = 1, KMPP_ROWS_BUFFER = 2 };
+enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
+
 /* Optional knobs of kmpp_seed (pass NULL for defaults). */
 typedef struct kmpp_seed_opts {
   uint32_t instance;    /* Philox instance id: counter word 1 (default 0) */
   int32_t threads;      /* threads per workgroup of the seed pass: 0 (tuned), 256 or 512 */
   int32_t rows_per_tile;/* rows per workgroup tile: 0 (tuned) or a positive count */
   int16_t loads_per_lane; /* 16-byte row loads in flight per lane: 0 (tuned), 8 or 16 */
-  int16_t nontemporal;  /* row loads: -1 (tuned; non-temporal when the rows exceed 256 MiB),
-                           0 cached, 1 non-temporal */
+  int16_t row_loads;    /* how the passes read the rows: -1 tuned (non-temporal when the rows
+                           exceed 256 MiB), KMPP_ROWS_CACHED, KMPP_ROWS_NONTEMPORAL or
+                           KMPP_ROWS_BUFFER */
   float* out_recheck;   /* device [K*2] or NULL.  Precision forms: for each draw m >= 1,
                            [2m] = D of the drawn row from the quantised rows before it is
                            committed, [2m+1] = its FP32 nearest distance recomputed from the
                            original FP32 row against the previous seeds. */
   void* step_events;    /* host array of 2K hipEvent_t or NULL: [2m-2] and [2m-1] track the
                            start and the stop of pass m's kernel (profiling only) */
+  int32_t centre_source;/* where the passes take the current centre from: 0 (default: LDS),
+                           KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR or KMPP_CENTRE_GLOBAL */
+  int32_t reserved;     /* 0 */
 } kmpp_seed_opts;
 
 /*

@@ -24,7 +24,7 @@ bool valid_dtype(int dtype) { return dtype == KMPP_F32 || dtype == KMPP_BF16 || 
 
 // ---- tuning table: (dtype, d) -> launch schedule
 struct SeedTune {
-  int threads, rpt, u, ntl;  // u, ntl: 0 / -1 = automatic
+  int threads, rpt, u, ntl;  // u, ntl (row path): 0 / -1 = automatic
 };
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, SeedTune> g_tune;
@@ -58,13 +58,15 @@ SeedLayout seed_layout(int64_t N, int K) {
   return L;
 }
 
-const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, bool ntl) {
+const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, int rl, int cs) {
   const auto& vs = seed_variants();
   const int eb = elem_bytes(dtype);
   for (int uu : {u, 8})
     for (const auto& v : vs)
-      if (v.fmt == dtype && v.nt == nt && v.dexact == d && (d * eb) % v.cb == 0 && v.u == uu && v.ntl == ntl)
+      if (v.fmt == dtype && v.nt == nt && v.dexact == d && (d * eb) % v.cb == 0 && v.u == uu && v.rl == rl &&
+          v.cs == cs)
         return &v;
+  if (cs != CEN_LDS || rl == ROW_BUFFER) return nullptr;  // memory-space variants: exact widths only
   const SeedVariant* best = nullptr;
   for (const auto& v : vs)
     if (v.fmt == dtype && v.nt == nt && v.dexact < 0 && -v.dexact >= d)
@@ -88,9 +90,12 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   if (opts && opts->threads) nt = opts->threads;
   if (opts && opts->rows_per_tile > 0) rpt = opts->rows_per_tile;
   if (opts && opts->loads_per_lane > 0) u = opts->loads_per_lane;
-  if (opts && opts->nontemporal >= 0) ntl = opts->nontemporal ? 1 : 0;
+  if (opts && opts->row_loads >= 0) ntl = opts->row_loads;
+  int cs = CEN_LDS;
+  if (opts && opts->centre_source) cs = opts->centre_source - 1;
   if (nt != 256 && nt != 512) return KMPP_E_UNSUPPORTED;
-  const SeedVariant* v = pick_seed_variant(dtype, d, nt, u, ntl != 0);
+  if (ntl < ROW_CACHED || ntl > ROW_BUFFER || cs < CEN_LDS || cs > CEN_GLOBAL) return KMPP_E_INVALID;
+  const SeedVariant* v = pick_seed_variant(dtype, d, nt, u, ntl, cs);
   if (!v) return KMPP_E_UNSUPPORTED;
   const int64_t it = v->rows_per_iter;
   if (rpt <= 0) {
@@ -102,6 +107,8 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   const int64_t min_r = (N + kMaxTiles - 1) / kMaxTiles;
   if (r < min_r) r = (min_r + it - 1) / it * it;
   if (r > (int64_t)1 << 30) return KMPP_E_UNSUPPORTED;
+  // a buffer resource spans one tile with 32-bit byte offsets
+  if (v->rl == ROW_BUFFER && r * d * elem_bytes(dtype) > ((int64_t)1 << 31)) return KMPP_E_UNSUPPORTED;
   *var = v;
   *rpt_out = (int)r;
   *ntiles_out = (int)((N + r - 1) / r);

@@ -98,10 +98,33 @@ struct Raw<1> { using T = uint8_t; };
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
-// One CB-byte chunk through a global pointer.  NTL: a non-temporal load
-// (streamed data read once per pass that does not fit the caches).
-template <int CB, bool NTL = false>
+// Where a pass reads the point rows from (the seed-pass kernels take one as
+// a template parameter):
+//   ROW_CACHED       plain global loads, cached in L2 and the last-level cache;
+//   ROW_NONTEMPORAL  non-temporal global loads, for rows read once per pass
+//                    that do not fit the caches;
+//   ROW_BUFFER       loads through a buffer resource: a 128-bit descriptor
+//                    (base, size) held in scalar registers, 32-bit offsets,
+//                    and a hardware range check that returns 0 outside it --
+//                    the read-only, descriptor-addressed path nearest to a
+//                    texture fetch.
+enum : int { ROW_CACHED = 0, ROW_NONTEMPORAL = 1, ROW_BUFFER = 2 };
+
+// Where every lane of a seed pass takes the current centre from (Section II
+// compares keeping the centroids in global and in constant memory):
+//   CEN_LDS     the workgroup copies the row into LDS once, lanes read their
+//               slice from there (one barrier);
+//   CEN_SCALAR  scalar loads of the whole row into SGPRs through the scalar
+//               data cache (uniform, read-only: the constant-cache path),
+//               exact widths only;
+//   CEN_GLOBAL  every lane loads its own slice with vector loads (L2 hits
+//               after the first workgroup).
+enum : int { CEN_LDS = 0, CEN_SCALAR = 1, CEN_GLOBAL = 2 };
+
+// One CB-byte chunk through a global pointer (ROW_CACHED, ROW_NONTEMPORAL).
+template <int CB, int RL = ROW_CACHED>
 __device__ __forceinline__ typename Raw<CB>::T load_raw(gptr<const char> p) {
+  constexpr bool NTL = RL == ROW_NONTEMPORAL;
   if constexpr (CB == 16) {
     const v4u v = NTL ? __builtin_nontemporal_load((gptr<const v4u>)p) : *(gptr<const v4u>)p;
     return make_uint4(v.x, v.y, v.z, v.w);
@@ -111,6 +134,31 @@ __device__ __forceinline__ typename Raw<CB>::T load_raw(gptr<const char> p) {
   } else {
     using T = typename Raw<CB>::T;
     return NTL ? __builtin_nontemporal_load((gptr<const T>)p) : *(gptr<const T>)p;
+  }
+}
+
+// Buffer resource over `bytes` bytes at `base` (raw, stride 0; the third
+// descriptor word selects 32-bit data on gfx9-family chips).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rows_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// One CB-byte chunk at byte offset `off` of a buffer resource (ROW_BUFFER);
+// chunks past the resource's size read as zero.
+template <int CB>
+__device__ __forceinline__ typename Raw<CB>::T load_raw_buf(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (CB == 16) {
+    const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else if constexpr (CB == 8) {
+    const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return make_uint2(v.x, v.y);
+  } else if constexpr (CB == 4) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  } else if constexpr (CB == 2) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+  } else {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
   }
 }
 

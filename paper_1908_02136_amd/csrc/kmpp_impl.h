@@ -40,7 +40,8 @@ struct SeedVariant {
   int dexact;        // > 0: exactly this d with 16-byte (or 8-byte) chunks; < 0: any d <= -dexact
   int cb, g, cpl, u;
   bool full;
-  bool ntl;          // non-temporal row loads
+  int rl;            // row path: ROW_CACHED, ROW_NONTEMPORAL or ROW_BUFFER
+  int cs;            // centre source: CEN_LDS, CEN_SCALAR or CEN_GLOBAL
   int nt;
   int rows_per_iter; // rows one workgroup covers per loop iteration
   const void* fn;

@@ -224,11 +224,13 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
 }
 
 // ---------------------------------------------------------------- S2
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL>
+// One pass: the row path RL and the centre source CS are template
+// parameters (the memory spaces Section II compares).
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS>
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
-  using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, NTL>;
+  using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, RL>;
   constexpr int NW = NT / 64;
-  extern __shared__ float cs[];  // centre row, d floats
+  extern __shared__ float cs[];  // centre row, d floats (CEN_LDS)
   __shared__ double red[NW];
 
   const int tid = threadIdx.x;
@@ -240,13 +242,25 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   // centre c_{pass-1}: the original FP32 row of the previous seed
   const int64_t cidx = p.idx[p.pass - 1];
   const float* cg = p.X + cidx * (int64_t)d;
-  for (int j = tid; j < d; j += NT) cs[j] = cg[j];
   const int64_t prev = (FMT != FMT_F32) ? cidx : -1;
-  __syncthreads();
-  if (blockIdx.x == 0 && p.pass > 1)
-    for (int j = tid; j < d; j += NT) p.centers[(int64_t)(p.pass - 1) * d + j] = cs[j];
   S st;
-  st.init(cs, d);
+  st.layout();
+  if constexpr (CS == CEN_SCALAR) {
+    st.set_centre_uniform(cg);
+  } else if constexpr (CS == CEN_GLOBAL) {
+    // a zero the compiler cannot see as uniform keeps these vector loads
+    // even where every lane reads the same address (one lane per row)
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    st.set_centre(as_global(cg) + vzero, d);
+  } else {
+    for (int j = tid; j < d; j += NT) cs[j] = cg[j];
+    __syncthreads();
+    st.set_centre(cs, d);
+  }
+  if (blockIdx.x == 0 && p.pass > 1)
+    for (int j = tid; j < d; j += NT) p.centers[(int64_t)(p.pass - 1) * d + j] = CS == CEN_LDS ? cs[j] : cg[j];
+  st.set_rows(p.xs, t0, t1, d);
 
   double acc = 0.0;
   float* D = p.D;
@@ -268,7 +282,7 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
 }
 
 // ---------------------------------------------------------------- registry
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS = CEN_LDS>
 static SeedVariant make_variant(int dexact) {
   SeedVariant v;
   v.fmt = FMT;
@@ -279,9 +293,10 @@ static SeedVariant make_variant(int dexact) {
   v.u = U;
   v.full = FULL;
   v.nt = NT;
-  v.ntl = NTL;
+  v.rl = RL;
+  v.cs = CS;
   v.rows_per_iter = (NT / 64) * U * (64 / G);
-  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, NTL>);
+  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS>);
   return v;
 }
 
@@ -306,28 +321,43 @@ static SeedVariant make_variant(int dexact) {
 
 // Any d: one element per chunk, G = min(64, pow2 >= d) lanes per row.
 #define KMPP_GENERIC(NT)                                                                                    \
-  make_variant<FMT_F32, 4, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT, false>(-2), \
-      make_variant<FMT_F32, 4, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT, false>(-8), \
-      make_variant<FMT_F32, 4, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT, false>(-32), \
-      make_variant<FMT_F32, 4, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT, false>(-256), \
-      make_variant<FMT_F32, 4, 64, 16, 2, false, NT, false>(-1024),                                         \
-      make_variant<FMT_F32, 4, 64, 64, 1, false, NT, false>(-4096),                                         \
-      make_variant<FMT_BF16, 2, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_BF16, 2, 2, 1, 8, false, NT, false>(-2), \
-      make_variant<FMT_BF16, 2, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_BF16, 2, 8, 1, 8, false, NT, false>(-8), \
-      make_variant<FMT_BF16, 2, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_BF16, 2, 32, 1, 8, false, NT, false>(-32), \
-      make_variant<FMT_BF16, 2, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_BF16, 2, 64, 4, 8, false, NT, false>(-256), \
-      make_variant<FMT_BF16, 2, 64, 16, 2, false, NT, false>(-1024),                                        \
-      make_variant<FMT_BF16, 2, 64, 64, 1, false, NT, false>(-4096),                                        \
-      make_variant<FMT_FP8, 1, 1, 1, 8, false, NT, false>(-1), make_variant<FMT_FP8, 1, 2, 1, 8, false, NT, false>(-2), \
-      make_variant<FMT_FP8, 1, 4, 1, 8, false, NT, false>(-4), make_variant<FMT_FP8, 1, 8, 1, 8, false, NT, false>(-8), \
-      make_variant<FMT_FP8, 1, 16, 1, 8, false, NT, false>(-16), make_variant<FMT_FP8, 1, 32, 1, 8, false, NT, false>(-32), \
-      make_variant<FMT_FP8, 1, 64, 1, 8, false, NT, false>(-64), make_variant<FMT_FP8, 1, 64, 4, 8, false, NT, false>(-256), \
-      make_variant<FMT_FP8, 1, 64, 16, 2, false, NT, false>(-1024),                                         \
-      make_variant<FMT_FP8, 1, 64, 64, 1, false, NT, false>(-4096)
+  make_variant<FMT_F32, 4, 1, 1, 8, false, NT, ROW_CACHED>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT, ROW_CACHED>(-2), \
+      make_variant<FMT_F32, 4, 4, 1, 8, false, NT, ROW_CACHED>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT, ROW_CACHED>(-8), \
+      make_variant<FMT_F32, 4, 16, 1, 8, false, NT, ROW_CACHED>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT, ROW_CACHED>(-32), \
+      make_variant<FMT_F32, 4, 64, 1, 8, false, NT, ROW_CACHED>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT, ROW_CACHED>(-256), \
+      make_variant<FMT_F32, 4, 64, 16, 2, false, NT, ROW_CACHED>(-1024),                                         \
+      make_variant<FMT_F32, 4, 64, 64, 1, false, NT, ROW_CACHED>(-4096),                                         \
+      make_variant<FMT_BF16, 2, 1, 1, 8, false, NT, ROW_CACHED>(-1), make_variant<FMT_BF16, 2, 2, 1, 8, false, NT, ROW_CACHED>(-2), \
+      make_variant<FMT_BF16, 2, 4, 1, 8, false, NT, ROW_CACHED>(-4), make_variant<FMT_BF16, 2, 8, 1, 8, false, NT, ROW_CACHED>(-8), \
+      make_variant<FMT_BF16, 2, 16, 1, 8, false, NT, ROW_CACHED>(-16), make_variant<FMT_BF16, 2, 32, 1, 8, false, NT, ROW_CACHED>(-32), \
+      make_variant<FMT_BF16, 2, 64, 1, 8, false, NT, ROW_CACHED>(-64), make_variant<FMT_BF16, 2, 64, 4, 8, false, NT, ROW_CACHED>(-256), \
+      make_variant<FMT_BF16, 2, 64, 16, 2, false, NT, ROW_CACHED>(-1024),                                        \
+      make_variant<FMT_BF16, 2, 64, 64, 1, false, NT, ROW_CACHED>(-4096),                                        \
+      make_variant<FMT_FP8, 1, 1, 1, 8, false, NT, ROW_CACHED>(-1), make_variant<FMT_FP8, 1, 2, 1, 8, false, NT, ROW_CACHED>(-2), \
+      make_variant<FMT_FP8, 1, 4, 1, 8, false, NT, ROW_CACHED>(-4), make_variant<FMT_FP8, 1, 8, 1, 8, false, NT, ROW_CACHED>(-8), \
+      make_variant<FMT_FP8, 1, 16, 1, 8, false, NT, ROW_CACHED>(-16), make_variant<FMT_FP8, 1, 32, 1, 8, false, NT, ROW_CACHED>(-32), \
+      make_variant<FMT_FP8, 1, 64, 1, 8, false, NT, ROW_CACHED>(-64), make_variant<FMT_FP8, 1, 64, 4, 8, false, NT, ROW_CACHED>(-256), \
+      make_variant<FMT_FP8, 1, 64, 16, 2, false, NT, ROW_CACHED>(-1024),                                         \
+      make_variant<FMT_FP8, 1, 64, 64, 1, false, NT, ROW_CACHED>(-4096)
+
+// Memory-space variants (FP32 rows, U = 8, 256 threads) of the widths of the
+// two-dimensional points of the paper's experiments and of the 32-, 64- and
+// 128-wide workloads: every centre source with every row path.
+#define KMPP_SPACE_D(CB, G, DX)                                                                               \
+  make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_BUFFER, CEN_LDS>(DX),                                     \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_CACHED, CEN_SCALAR>(DX),                              \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_NONTEMPORAL, CEN_SCALAR>(DX),                         \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_BUFFER, CEN_SCALAR>(DX),                              \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_CACHED, CEN_GLOBAL>(DX),                              \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_NONTEMPORAL, CEN_GLOBAL>(DX),                         \
+      make_variant<FMT_F32, CB, G, 1, 8, true, 256, ROW_BUFFER, CEN_GLOBAL>(DX)
+#define KMPP_SPACES KMPP_SPACE_D(8, 1, 2), KMPP_SPACE_D(16, 8, 32), KMPP_SPACE_D(16, 16, 64), KMPP_SPACE_D(16, 32, 128)
 
 const std::vector<SeedVariant>& seed_variants() {
-  static const std::vector<SeedVariant> v = {KMPP_EXACT(256, false), KMPP_EXACT(256, true), KMPP_EXACT(512, false),
-                                             KMPP_EXACT(512, true), KMPP_GENERIC(256), KMPP_GENERIC(512)};
+  static const std::vector<SeedVariant> v = {KMPP_EXACT(256, ROW_CACHED), KMPP_EXACT(256, ROW_NONTEMPORAL),
+                                             KMPP_EXACT(512, ROW_CACHED), KMPP_EXACT(512, ROW_NONTEMPORAL),
+                                             KMPP_GENERIC(256),           KMPP_GENERIC(512),
+                                             KMPP_SPACES};
   return v;
 }
 

@@ -14,9 +14,10 @@ namespace kmpp {
 // shuffles, and U loads per lane are issued before any is consumed.
 // iter() handles the R = U*64/G rows of one wave starting at `base` and
 // hands every row's new nearest distance to `sink(row, dnew)`; a row's
-// arithmetic depends only on the template parameters.  NTL selects
-// non-temporal row loads for inputs larger than the last-level cache.
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, bool NTL = false>
+// arithmetic depends only on the template parameters, not on where the
+// rows (RL: ROW_CACHED, ROW_NONTEMPORAL or ROW_BUFFER) or the centre come
+// from.
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL = ROW_CACHED>
 struct Streamer {
   static constexpr int EB = ElemBytes<FMT>::value;
   static constexpr int VEC = CB / EB;
@@ -28,6 +29,9 @@ struct Streamer {
 
   float cen[CPL][VEC];
   int sub, rg, wave;
+  // ROW_BUFFER: a resource over this workgroup's rows [rfirst, r1)
+  __amdgpu_buffer_rsrc_t rs;
+  int64_t rfirst;
 
   // The loaded state of one iteration: rows, FP8 row scales, old D.
   struct Batch {
@@ -43,13 +47,45 @@ struct Streamer {
     rg = lane / G;
   }
 
-  __device__ __forceinline__ void set_centre(const float* cs, int d) {
+  // Each lane reads its own slice of the centre (from LDS, or per lane from
+  // global memory).
+  template <class Ptr>
+  __device__ __forceinline__ void set_centre(Ptr cs, int d) {
     const int nchunk = d / VEC;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
       const int c = sub + G * k;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) cen[k][e] = (FULL || c < nchunk) ? cs[c * VEC + e] : 0.0f;
+    }
+  }
+
+  // The whole centre through the scalar unit: the same address in every
+  // lane, so the loads are scalar (scalar data cache, values in SGPRs), then
+  // each lane selects its slice.  Exact widths only (d = G * CPL * VEC).
+  __device__ __forceinline__ void set_centre_uniform(const float* cg) {
+    static_assert(FULL, "scalar centre loads need a compile-time width");
+    constexpr int DD = G * CPL * VEC;
+    float c[DD];
+#pragma unroll
+    for (int j = 0; j < DD; ++j) c[j] = cg[j];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        float v = c[(G * k) * VEC + e];
+#pragma unroll
+        for (int s = 1; s < G; ++s) v = (sub == s) ? c[(s + G * k) * VEC + e] : v;
+        cen[k][e] = v;
+      }
+  }
+
+  // ROW_BUFFER: bind the rows [r0, r1) (at most 2^31 bytes).
+  __device__ __forceinline__ void set_rows(const void* xs, int64_t r0, int64_t r1, int d) {
+    if constexpr (RL == ROW_BUFFER) {
+      const int64_t rb = (int64_t)d * EB;
+      rs = make_rows_rsrc(static_cast<const char*>(xs) + r0 * rb, (uint32_t)((r1 - r0) * rb));
+      rfirst = r0;
     }
   }
 
@@ -76,15 +112,29 @@ struct Streamer {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       int64_t row = base + u * RPL + rg;
-      row = row < r1 ? row : r1 - 1;  // in bounds; the value is discarded
-      const gptr<const char> rp = xb + row * rb;
+      if constexpr (RL == ROW_BUFFER) {
+        // rows past the tile read as zero through the range check
+        const uint32_t ro = (uint32_t)((row - rfirst) * rb);
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const int c = sub + G * k;
-        if (FULL || c < nchunk)
-          b.raw[u][k] = load_raw<CB, NTL>(rp + (int64_t)c * CB);
-        else
-          b.raw[u][k] = RawT{};
+        for (int k = 0; k < CPL; ++k) {
+          const int c = sub + G * k;
+          if (FULL || c < nchunk)
+            b.raw[u][k] = load_raw_buf<CB>(rs, ro + (uint32_t)(c * CB));
+          else
+            b.raw[u][k] = RawT{};
+        }
+        row = row < r1 ? row : r1 - 1;
+      } else {
+        row = row < r1 ? row : r1 - 1;  // in bounds; the value is discarded
+        const gptr<const char> rp = xb + row * rb;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const int c = sub + G * k;
+          if (FULL || c < nchunk)
+            b.raw[u][k] = load_raw<CB, RL>(rp + (int64_t)c * CB);
+          else
+            b.raw[u][k] = RawT{};
+        }
       }
       if constexpr (FMT == FMT_FP8) b.sc[u] = exp2i((int)xe[row]);
     }

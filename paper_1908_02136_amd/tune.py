@@ -55,7 +55,7 @@ def tune_seed(kl, cases, quick):
                     for ntl in (0, 1):
                         try:
                             ms = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt,
-                                                            rows_per_tile=rpt, loads_per_lane=u, nontemporal=ntl))
+                                                            rows_per_tile=rpt, loads_per_lane=u, row_loads=ntl))
                         except kl.KmppError:
                             continue
                         print(f"seed dtype={dtype} d={d} N={N} K={K} threads={nt} rows={rpt} u={u} nt={ntl}: "
