@@ -86,6 +86,10 @@ def lib():
         L.kmo_fp8_quantize_rows.argtypes = [P, i64, i32, P, P]
         L.kmo_fp8_dequantize_rows.argtypes = [P, P, i64, i32, P]
         L.kmo_fp8_quantize_rows_fast.argtypes = [P, i64, i32, P, P, i32]
+        L.kmo_lloyd_update.argtypes = [P, i64, i32, P, i32, P, P, P]
+        L.kmo_lloyd_update.restype = ctypes.c_int
+        L.kmo_lloyd.argtypes = [P, i64, i32, i32, P, i32, P, P, P, i32]
+        L.kmo_lloyd.restype = ctypes.c_int
         L.kmo_fp8_encode_bisect.argtypes = [ctypes.c_double]
         L.kmo_fp8_encode_bisect.restype = ctypes.c_uint8
         _lib = L
@@ -190,6 +194,39 @@ def pair_dist(X, rows, C, cols) -> np.ndarray:
     out = np.zeros(rows.size, dtype=np.float64)
     lib().kmo_pair_dist(_ptr(X), X.shape[1], _ptr(rows), rows.size, _ptr(C), _ptr(cols), _ptr(out))
     return out
+
+
+# ---------------------------------------------------------------- Lloyd
+def lloyd_update(X, labels, C_prev):
+    """One centre update: the FP64 mean of every cluster's points in index
+    order, rounded to FP32; empty clusters keep their centre.  Returns
+    (C float32 [K, d], counts int64 [K])."""
+    X = _f32(X)
+    C_prev = _f32(C_prev)
+    K, d = C_prev.shape
+    lab = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+    C = np.zeros((K, d), dtype=np.float32)
+    n = np.zeros(K, dtype=np.int64)
+    st = lib().kmo_lloyd_update(_ptr(X), X.shape[0], d, _ptr(lab), K, _ptr(C_prev), _ptr(C), _ptr(n))
+    if st != OK:
+        raise ValueError("oracle: invalid arguments")
+    return C, n
+
+
+def lloyd(X, C0, iters: int, nthreads: int = 0):
+    """`iters` Lloyd iterations from centres C0.  Returns (C after the last
+    update, labels of the last assignment, cost [iters], changed [iters])."""
+    X = _f32(X)
+    C = _f32(C0).copy()
+    N, d = X.shape
+    K = C.shape[0]
+    lab = np.zeros(N, dtype=np.int32)
+    cost = np.zeros(iters, dtype=np.float64)
+    ch = np.zeros(iters, dtype=np.int64)
+    st = lib().kmo_lloyd(_ptr(X), N, d, K, _ptr(C), iters, _ptr(lab), _ptr(cost), _ptr(ch), nthreads)
+    if st != OK:
+        raise ValueError("oracle: invalid arguments")
+    return C, lab, cost, ch
 
 
 # ---------------------------------------------------------------- formats

@@ -474,3 +474,81 @@ void kmo_fp8_dequantize_rows(const uint8_t* q, const int8_t* ex, int64_t N, int3
     for (int32_t j = 0; j < d; ++j)
       out[i * (int64_t)d + j] = (float)ldexp(kmo_fp8_decode(q[i * (int64_t)d + j]), ex[i]);
 }
+
+/* ---- Lloyd iterations after seeding.  Section II says that once the
+ * initial centroids are chosen the clustering proceeds as in standard
+ * k-means; the output O of Algorithm 1 is the partition.  One iteration:
+ *   1. every point takes its nearest centre (kmo_assign's rule, ties to the
+ *      smallest index), and the cost is sum_i min_j ||x_i - c_j||^2;
+ *   2. every centre moves to the mean of its points.
+ * Readings: a centre with no points keeps its position; the mean is the
+ * FP64 sum in point-index order divided by the count, rounded to FP32 (the
+ * centres are FP32 arrays); the number of points whose label changed is
+ * counted against the previous iteration (all N in the first). */
+int kmo_lloyd_update(const float* X, int64_t N, int32_t d, const int32_t* labels, int32_t K, const float* C_prev,
+                     float* C_out, int64_t* counts) {
+  if (!X || !labels || !C_prev || !C_out || N < 0 || d < 1 || K < 1) return KMO_E_INVALID;
+  double* sum = (double*)calloc((size_t)K * (size_t)d, sizeof(double));
+  int64_t* n = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+  if (!sum || !n) {
+    free(sum);
+    free(n);
+    return KMO_E_INVALID;
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    const int32_t j = labels[i];
+    if (j < 0 || j >= K) {
+      free(sum);
+      free(n);
+      return KMO_E_INVALID;
+    }
+    n[j] += 1;
+    for (int32_t q = 0; q < d; ++q) sum[(int64_t)j * d + q] += (double)X[i * (int64_t)d + q];
+  }
+  for (int32_t j = 0; j < K; ++j) {
+    for (int32_t q = 0; q < d; ++q) {
+      const int64_t e = (int64_t)j * d + q;
+      C_out[e] = n[j] > 0 ? (float)(sum[e] / (double)n[j]) : C_prev[e];
+    }
+    if (counts) counts[j] = n[j];
+  }
+  free(sum);
+  free(n);
+  return KMO_OK;
+}
+
+/* `iters` iterations from the centres in C (updated in place).  labels: the
+ * last iteration's assignment (against the centres before its update);
+ * cost[t], changed[t]: of iteration t's assignment (nullable). */
+int kmo_lloyd(const float* X, int64_t N, int32_t d, int32_t K, float* C, int32_t iters, int32_t* labels,
+              double* cost, int64_t* changed, int32_t nthreads) {
+  if (!X || !C || !labels || N < 1 || d < 1 || K < 1 || iters < 0) return KMO_E_INVALID;
+  double* mind = (double*)malloc(sizeof(double) * (size_t)N);
+  int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  float* Cn = (float*)malloc(sizeof(float) * (size_t)K * (size_t)d);
+  if (!mind || !prev || !Cn) {
+    free(mind);
+    free(prev);
+    free(Cn);
+    return KMO_E_INVALID;
+  }
+  for (int64_t i = 0; i < N; ++i) prev[i] = -1;
+  for (int32_t t = 0; t < iters; ++t) {
+    kmo_assign(X, N, d, C, K, labels, mind, NULL, nthreads);
+    double s = 0.0;
+    int64_t ch = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      s += mind[i];
+      ch += labels[i] != prev[i];
+      prev[i] = labels[i];
+    }
+    if (cost) cost[t] = s;
+    if (changed) changed[t] = ch;
+    kmo_lloyd_update(X, N, d, labels, K, C, Cn, NULL);
+    memcpy(C, Cn, sizeof(float) * (size_t)K * (size_t)d);
+  }
+  free(mind);
+  free(prev);
+  free(Cn);
+  return KMO_OK;
+}
