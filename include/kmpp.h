@@ -143,7 +143,8 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
  *
  * X            [N, d] rows in `dtype` (FP32, BF16 or FP8 with X_exp)
  * C            FP32 [K, d] seeds
- * out_labels   int32 [N]: index of the nearest seed; ties -> smallest index
+ * out_labels   int32 [N]: index of the nearest seed; ties -> smallest index;
+ *              -1 for a row with no comparable distance (NaN in the row)
  * out_mind     FP32 [N] or NULL: squared distance to that seed, direct form
  * Scores ||c||^2 - 2<x,c> come from matrix-core products with FP32
  * accumulation; rows whose best and second-best scores are closer than the
@@ -154,6 +155,36 @@ size_t kmpp_assign_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtyp
 int kmpp_assign(const void* X, const int8_t* X_exp, int32_t dtype, const float* C, int64_t N, int32_t d,
                 int32_t K, int32_t* out_labels, float* out_mind, void* workspace, size_t ws_bytes,
                 void* stream);
+
+/*
+ * Lloyd iterations after seeding.  Section II: once the initial centroids
+ * are chosen, the clustering proceeds as standard k-means, whose result is
+ * the partition O of Algorithm 1.  One iteration assigns every row to its
+ * nearest centre (the kmpp_assign rule) and then moves every centre to the
+ * mean of its rows; a centre with no rows keeps its position.
+ *
+ * X, X_exp, dtype  rows as for kmpp_assign (means of the dequantised rows)
+ * C                FP32 [K, d], 16-byte aligned, in/out: the starting
+ *                  centres (e.g. kmpp_seed's out_centers), replaced by the
+ *                  centres after `iters` updates
+ * iters            >= 0 iterations, all enqueued (no host synchronisation)
+ * out_labels       int32 [N]: the last iteration's assignment (against the
+ *                  centres before its update; call kmpp_assign on the final
+ *                  C for labels that match it)
+ * out_cost         FP64 [iters] or NULL: sum over rows of the squared
+ *                  distance to the assigned centre, per iteration
+ * out_changed      int64 [iters] or NULL: rows whose label differs from the
+ *                  previous iteration (N in the first)
+ * out_counts       int32 [K] or NULL: cluster sizes of the last assignment
+ * Means are FP64 divisions of 64-bit fixed-point cluster sums (scale 2^F,
+ * F = 62 - e - ceil(log2 N), max|x| < 2^e), rounded to FP32: every run
+ * gives the same bits.  Device status (kmpp_status on this workspace):
+ * KMPP_E_NONFINITE if X holds NaN or Inf.
+ */
+size_t kmpp_lloyd_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype);
+int kmpp_lloyd(const void* X, const int8_t* X_exp, int32_t dtype, int64_t N, int32_t d, int32_t K, float* C,
+               int32_t iters, int32_t* out_labels, double* out_cost, int64_t* out_changed, int32_t* out_counts,
+               void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Storage formats for the precision forms.

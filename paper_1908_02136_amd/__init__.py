@@ -32,6 +32,7 @@ MAX_D = 4096
 # Every symbol the header declares (checked by the test suite).
 SYMBOLS = [
     "kmpp_seed_workspace_bytes", "kmpp_seed", "kmpp_assign_workspace_bytes", "kmpp_assign", "kmpp_quantize",
+    "kmpp_lloyd_workspace_bytes", "kmpp_lloyd",
     "kmpp_batched_workspace_bytes", "kmpp_seed_batched_prepare", "kmpp_seed_batched_launch",
     "kmpp_seed_batched", "kmpp_status", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
     "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_strerror", "kmpp_version",
@@ -77,6 +78,10 @@ def lib() -> ctypes.CDLL:
     L.kmpp_assign_workspace_bytes.restype = sz
     L.kmpp_assign.argtypes = [P, P, i32, P, i64, i32, i32, P, P, P, sz, P]
     L.kmpp_assign.restype = ctypes.c_int
+    L.kmpp_lloyd_workspace_bytes.argtypes = [i64, i32, i32, i32]
+    L.kmpp_lloyd_workspace_bytes.restype = sz
+    L.kmpp_lloyd.argtypes = [P, P, i32, i64, i32, i32, P, i32, P, P, P, P, P, sz, P]
+    L.kmpp_lloyd.restype = ctypes.c_int
     L.kmpp_quantize.argtypes = [P, i64, i32, i32, P, P, P]
     L.kmpp_quantize.restype = ctypes.c_int
     L.kmpp_batched_workspace_bytes.argtypes = [ctypes.POINTER(Instance), i32]
@@ -212,6 +217,32 @@ def kmpp_assign(X: torch.Tensor, C: torch.Tensor, *, X_exp=None, dtype: int = KM
                            _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "kmpp_assign")
     return out_labels, out_mind, ws
+
+
+# ---------------------------------------------------------------- Lloyd
+def kmpp_lloyd_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> int:
+    return int(lib().kmpp_lloyd_workspace_bytes(N, d, K, dtype))
+
+
+def kmpp_lloyd(X: torch.Tensor, C: torch.Tensor, iters: int, *, X_exp=None, dtype: int = KMPP_F32,
+               out_labels=None, out_cost=None, out_changed=None, out_counts=None, ws=None, stream=None):
+    """`iters` Lloyd iterations from the centres C (FP32 [K, d], updated in
+    place).  X is [N, d] in `dtype`.  Returns (C, labels int32 [N],
+    cost FP64 [iters], changed int64 [iters], counts int32 [K], ws)."""
+    _require_cuda(X, C, X_exp)
+    N, d = X.shape
+    K = C.shape[0]
+    dev = X.device
+    out_labels = torch.empty(N, dtype=torch.int32, device=dev) if out_labels is None else out_labels
+    out_cost = torch.empty(max(iters, 1), dtype=torch.float64, device=dev) if out_cost is None else out_cost
+    out_changed = torch.empty(max(iters, 1), dtype=torch.int64, device=dev) if out_changed is None else out_changed
+    out_counts = torch.empty(K, dtype=torch.int32, device=dev) if out_counts is None else out_counts
+    if ws is None:
+        ws = workspace(kmpp_lloyd_workspace_bytes(N, d, K, dtype), dev)
+    rc = lib().kmpp_lloyd(_ptr(X), _ptr(X_exp), dtype, N, d, K, _ptr(C), iters, _ptr(out_labels), _ptr(out_cost),
+                          _ptr(out_changed), _ptr(out_counts), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "kmpp_lloyd")
+    return C, out_labels, out_cost[:iters], out_changed[:iters], out_counts, ws
 
 
 # ---------------------------------------------------------------- batched

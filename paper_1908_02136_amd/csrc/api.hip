@@ -185,6 +185,24 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
   return KMPP_OK;
 }
 
+size_t kmpp_lloyd_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype) {
+  if (N < 1 || K < 1 || d < 1 || d > KMPP_MAX_D || !valid_dtype(dtype)) return 0;
+  return lloyd_workspace(N, d, K, dtype);
+}
+
+int kmpp_lloyd(const void* X, const int8_t* X_exp, int32_t dtype, int64_t N, int32_t d, int32_t K, float* C,
+               int32_t iters, int32_t* out_labels, double* out_cost, int64_t* out_changed, int32_t* out_counts,
+               void* workspace, size_t ws_bytes, void* stream) {
+  if (!X || !C || !out_labels || !workspace) return KMPP_E_INVALID;
+  if (N < 1 || K < 1 || N > INT32_MAX || d < 1 || d > KMPP_MAX_D || iters < 0 || !valid_dtype(dtype))
+    return KMPP_E_INVALID;
+  if (dtype == KMPP_FP8_E4M3 && !X_exp) return KMPP_E_INVALID;
+  if (!aligned(X, 16) || !aligned(C, 16) || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  if (ws_bytes < lloyd_workspace(N, d, K, dtype)) return KMPP_E_WORKSPACE;
+  return launch_lloyd(X, X_exp, dtype, N, d, K, C, iters, out_labels, out_cost, out_changed, out_counts, workspace,
+                      ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 int kmpp_quantize(const float* X, int64_t N, int32_t d, int32_t dtype, void* Xq, int8_t* Xq_exp, void* stream) {
   if (!X || !Xq || N < 1 || d < 1 || d > KMPP_MAX_D) return KMPP_E_INVALID;
   if (dtype != KMPP_BF16 && dtype != KMPP_FP8_E4M3) return KMPP_E_INVALID;

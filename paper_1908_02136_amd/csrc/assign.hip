@@ -375,8 +375,9 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
       }
     }
     if (lane == 0) {
-      p.labels[row] = bi;
-      if (p.mind) p.mind[row] = best;
+      // no comparable distance (NaN in the row or the centres): label -1
+      p.labels[row] = bi < p.K ? bi : -1;
+      if (p.mind) p.mind[row] = bi < p.K ? best : __builtin_nanf("");
     }
   }
 }

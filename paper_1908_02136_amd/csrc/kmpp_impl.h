@@ -62,6 +62,12 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
                   int32_t* labels, float* mind, void* ws, size_t ws_bytes, hipStream_t stream);
 size_t assign_workspace(int64_t N, int d, int K, int dtype);
 
+// Lloyd iterations
+size_t lloyd_workspace(int64_t N, int d, int K, int dtype);
+int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d, int K, float* C, int iters,
+                 int32_t* out_labels, double* out_cost, int64_t* out_changed, int32_t* out_counts, void* ws,
+                 size_t ws_bytes, hipStream_t stream);
+
 // Quantisers
 int launch_quantize(const float* X, int64_t N, int d, int dtype, void* Xq, int8_t* Xq_exp, hipStream_t stream);
 

@@ -117,3 +117,17 @@ def test_unitsphere_bf16_sample(kl):
     lab, mind = run_assign(kl, q, C, dtype=kl.KMPP_BF16)
     Xd = oracle.bf16_decode(oracle.bf16_encode(w.X.cpu().numpy()))
     check_assign(Xd, C.cpu().numpy(), lab, mind)
+
+
+@pytest.mark.parametrize("d", [8, 32, 300])
+def test_nan_row_gets_label_minus_one(kl, d):
+    # a row with a NaN has no comparable distance: label -1, distance NaN;
+    # every other row is unaffected
+    N, K = 3000, 20
+    Xh = kmpp_synth.gaussian(N, d, seed=77 + d)
+    Ch = Xh[:K].clone()
+    Xh[123, d // 2] = float("nan")
+    lab, mind = run_assign(kl, Xh.cuda(), Ch.cuda())
+    assert lab[123] == -1 and np.isnan(mind[123])
+    keep = np.arange(N) != 123
+    check_assign(Xh.numpy()[keep], Ch.numpy(), lab[keep], mind[keep])
