@@ -19,6 +19,8 @@ seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
                 workloads, and the batched form (512 uneven instances in one
                 persistent launch) against 512 plain calls; --no-forms skips
                 them
+  lloyd         Lloyd iterations after seeding (per-iteration time, the
+                centre update alone); --no-lloyd skips them
   memory_spaces the paper's memory-space comparison (Section II, Figs. 2c
                 and 3c) on this chip: every row path (cached, non-temporal,
                 buffer descriptor) x centre source (LDS, scalar, global) on
@@ -257,6 +259,49 @@ def batched_form(kl, reps):
             "frac_hbm": xb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def lloyd_iterations(kl, name, w, iters=5, reps=2, dtype=0):
+    """Lloyd iterations after seeding: per-iteration time, and the centre
+    update (fixed-point cluster sums, atomics) as the difference between an
+    iteration and an assignment alone."""
+    X, N, d, K = w.X, w.N, w.d, w.K
+    Xq = E = None
+    if dtype:
+        Xq, E = kl.kmpp_quantize(X, dtype)
+    Xa = X if dtype == 0 else Xq
+    idx, C0, _, _ = kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype)
+    C = C0.clone()
+    lab = torch.empty(N, dtype=torch.int32, device="cuda")
+    cost = torch.empty(iters, dtype=torch.float64, device="cuda")
+    ch = torch.empty(iters, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(K, dtype=torch.int32, device="cuda")
+    ws = kl.workspace(kl.kmpp_lloyd_workspace_bytes(N, d, K, dtype), "cuda")
+
+    def run():
+        C.copy_(C0)
+        kl.kmpp_lloyd(Xa, C, iters, X_exp=E, dtype=dtype, out_labels=lab, out_cost=cost, out_changed=ch,
+                      out_counts=cnt, ws=ws)
+
+    run()
+    torch.cuda.synchronize()
+    ms = time_events(run, reps)
+    st = kl.kmpp_status(ws)
+    kl.kmpp_assign(Xa, C0, X_exp=E, dtype=dtype)
+    torch.cuda.synchronize()
+    ams = time_events(lambda: kl.kmpp_assign(Xa, C0, X_exp=E, dtype=dtype), reps)
+    it_ms = ms / iters
+    upd_ms = max(it_ms - ams, 1e-6)
+    elem = {0: 4, 1: 2, 2: 1}[dtype]
+    upd_bytes = N * d * elem + 12 * N + (N if dtype == 2 else 0)
+    c = cost.cpu().tolist()
+    res = {"workload": f"{name} N={N} d={d} K={K} {['f32', 'bf16', 'fp8'][dtype]}", "iters": iters,
+           "ms_per_iter": it_ms, "assign_ms": ams, "update_ms": upd_ms,
+           "update_GBps": upd_bytes / (upd_ms * 1e-3) / 1e9, "status": st,
+           "cost_first": c[0], "cost_last": c[-1], "changed": ch.cpu().tolist()}
+    _log(f"  lloyd {res['workload']}: {it_ms:.3f} ms/iter (assign {ams:.3f}, update {upd_ms:.3f} ms, "
+         f"{res['update_GBps']:.0f} GB/s), cost {c[0]:.6g} -> {c[-1]:.6g}, status {st}")
+    return res
+
+
 def memory_spaces(kl, reps=3):
     """The paper's memory-space experiment (Section II; Figs. 2c, 3c) on this
     chip: every row path x centre source at one launch schedule, on the
@@ -306,6 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched forms")
     ap.add_argument("--no-spaces", action="store_true", help="skip the memory-space comparison")
+    ap.add_argument("--no-lloyd", action="store_true", help="skip the Lloyd iterations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
@@ -400,6 +446,13 @@ def main():
             torch.cuda.empty_cache()
         forms["batched"] = batched_form(kl, reps=3)
         res["forms"] = forms
+    if not args.no_lloyd:
+        res["lloyd"] = [lloyd_iterations(kl, "plain", w, iters=10)]
+        wu = kmpp_synth.unitsphere(device="cuda")
+        res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3))
+        res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3, dtype=kl.KMPP_BF16))
+        del wu
+        torch.cuda.empty_cache()
     if not args.no_spaces:
         res["memory_spaces"] = memory_spaces(kl)
     if not args.no_cpu_baseline:

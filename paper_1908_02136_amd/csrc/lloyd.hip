@@ -13,9 +13,16 @@
 // 2^(-F-1) = 2^(e + ceil(log2 N) - 63): for N = 2^24 and max|x| = 100 that is
 // 2^-32, far below half a unit in the last place of an FP32 mean unless the
 // mean is about 2^13 times smaller than max|x|; integer-valued points are
-// summed exactly.  Each workgroup first adds its rows into a private copy of
-// the sums in LDS when K * d is small enough, then adds that copy to the
-// global sums once.
+// summed exactly.
+//
+// Accumulation without global atomics: the clusters are split into R ranges
+// whose sums fit in one workgroup's LDS, and W workgroups per range each
+// take every W-th group of rows.  A workgroup adds the rows whose label lies
+// in its range into LDS (integer LDS atomics), then writes its partial sums
+// to global memory; the finalize kernel adds the W partials of every sum in
+// a fixed order and divides.  Workgroups of all ranges are interleaved in
+// the grid, so the ranges read the same labels at about the same time and
+// the repeated label reads hit the caches; each row is read once.
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 
@@ -36,14 +43,16 @@ struct LloydParams {
   int64_t N;
   int32_t d, K;
   int32_t G, lgG;             // lanes per row (power of two <= 64) and its log2
+  int32_t R, Kr, W;           // cluster ranges, clusters per range, workgroups per range
   const int32_t* labels;      // this iteration's assignment
   const int32_t* prev;        // the previous iteration's, or null (first iteration)
   const float* mind;          // distance of every row to its centre
   float* C;                   // [K, d], updated in place
-  long long* acc;             // [K * d] fixed-point sums
-  int32_t* cnt;               // [K] cluster sizes
-  double* part;               // [gridDim] per-workgroup cost sums
-  int32_t nparts;
+  long long* pacc;            // [W, K * d] partial fixed-point sums
+  int32_t* pcnt;              // [W, K] partial cluster sizes
+  double* pcost;              // [W] partial costs (range 0)
+  uint32_t* pchg;             // [W] partial changed-label counts (range 0)
+  float* pamax;               // [max-pass workgroups] partial max |x|
   unsigned long long* changed;  // rows whose label changed, or null
   double* cost;               // sum of mind, or null
   int32_t* counts_out;        // cluster sizes out, or null
@@ -71,118 +80,246 @@ __device__ __forceinline__ int lloyd_F(const LloydParams& p) {
   return 62 - e - lgN;
 }
 
-__global__ void lloyd_reset_kernel(LloydCtl* lc) {
-  lc->status = KMPP_OK;
-  lc->amax_bits = 0u;
-}
+__global__ void lloyd_reset_kernel(LloydCtl* lc) { lc->status = KMPP_OK; }
 
 // max |x| over all rows; a NaN or infinite value sets KMPP_E_NONFINITE.
-template <int FMT>
-__global__ __launch_bounds__(256) void lloyd_absmax_kernel(LloydParams p) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = lane & (p.G - 1), rg = lane >> p.lgG;
-  const int rpw = 64 >> p.lgG;
-  float m = 0.0f;
-  bool bad = false;
-  for (int64_t row = ((int64_t)blockIdx.x * 4 + wave) * rpw + rg; row < p.N; row += (int64_t)gridDim.x * 4 * rpw)
-    for (int k = sub; k < p.d; k += p.G) {
-      const float a = fabsf(lx<FMT>(p, row, k));
-      bad |= !(a <= 3.4028235e38f);
-      m = fmaxf(m, a);
-    }
-  m = wave_minf(-m);
-  if (lane == 0) atomicMax(&p.lc->amax_bits, __float_as_uint(-m));
+// FP32 / BF16: the rows as one flat array in 16-byte chunks; FP8: row by
+// row (each row has its own scale).
+// One partial maximum per workgroup (no contended atomics); a one-workgroup
+// kernel reduces them.
+__device__ __forceinline__ void absmax_publish(const LloydParams& p, float m, bool bad) {
+  __shared__ float sh[4];
+  m = block_minf<256>(-m, sh);
+  if (threadIdx.x == 0) p.pamax[blockIdx.x] = -m;
   if (bad) raise_status(reinterpret_cast<Ctl*>(p.lc), KMPP_E_NONFINITE);
 }
 
-__global__ __launch_bounds__(256) void lloyd_clear_kernel(LloydParams p) {
-  const int64_t n = (int64_t)p.K * p.d;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p.acc[e] = 0;
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p.K; j += (int64_t)gridDim.x * 256) p.cnt[j] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && p.changed) *p.changed = 0ull;
+__global__ __launch_bounds__(256) void lloyd_absmax_final_kernel(LloydParams p, int n) {
+  __shared__ float sh[4];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmaxf(m, p.pamax[i]);
+  m = block_minf<256>(-m, sh);
+  if (threadIdx.x == 0) p.lc->amax_bits = __float_as_uint(-m);
 }
 
-// Cluster sums, sizes, the cost and the changed-label count of one
-// iteration.  G lanes per row, 64/G rows per wave, workgroups stride over
-// the rows in a fixed order (so the FP64 cost partials are reproducible).
-template <int FMT, bool LDS>
-__global__ __launch_bounds__(256) void lloyd_accum_kernel(LloydParams p) {
-  extern __shared__ long long sh_acc[];  // LDS: [K * d] sums, then [K] int sizes
-  __shared__ double red[4];
-  __shared__ unsigned int red_ch[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sub = lane & (p.G - 1), rg = lane >> p.lgG;
-  const int rpw = 64 >> p.lgG;
-  const int64_t kd = (int64_t)p.K * p.d;
-  long long* acc = LDS ? sh_acc : p.acc;
-  int* cnt = LDS ? reinterpret_cast<int*>(sh_acc + kd) : p.cnt;
-  if constexpr (LDS) {
-    for (int64_t e = tid; e < kd; e += 256) sh_acc[e] = 0;
-    for (int j = tid; j < p.K; j += 256) cnt[j] = 0;
-    __syncthreads();
+template <int FMT>
+__global__ __launch_bounds__(256) void lloyd_absmax_kernel(LloydParams p) {
+  float m = 0.0f;
+  bool bad = false;
+  if constexpr (FMT == FMT_FP8) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane & (p.G - 1), rg = lane >> p.lgG;
+    const int rpw = 64 >> p.lgG;
+    for (int64_t row = ((int64_t)blockIdx.x * 4 + wave) * rpw + rg; row < p.N;
+         row += (int64_t)gridDim.x * 4 * rpw)
+      for (int k = sub; k < p.d; k += p.G) {
+        const float a = fabsf(lx<FMT>(p, row, k));
+        bad |= !(a <= 3.4028235e38f);
+        m = fmaxf(m, a);
+      }
+  } else {
+    constexpr int VEC = 16 / ElemBytes<FMT>::value;
+    const int64_t n = p.N * (int64_t)p.d;
+    const int64_t nchunk = n / VEC;
+    const gptr<const char> xb = as_global(static_cast<const char*>(p.X));
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t c0 = (int64_t)blockIdx.x * 256 + threadIdx.x; c0 < nchunk; c0 += 4 * stride) {
+      uint4 raw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t c = c0 + u * stride;
+        raw[u] = c < nchunk ? load_raw<16>(xb + c * 16) : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float v[VEC];
+        decode<FMT, 16>(raw[u], v);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float a = fabsf(v[e]);
+          bad |= !(a <= 3.4028235e38f);
+          m = fmaxf(m, a);
+        }
+      }
+    }
+    // the elements after the last whole chunk
+    for (int64_t e = nchunk * VEC + (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
+      const float a = fabsf(lx<FMT>(p, e / p.d, (int)(e % p.d)));
+      bad |= !(a <= 3.4028235e38f);
+      m = fmaxf(m, a);
+    }
   }
+  absmax_publish(p, m, bad);
+}
+
+
+// Partial cluster sums of one iteration.  Workgroup (w, r) = blockIdx.x
+// (w * R + r) takes blocks of kLB * 64 consecutive rows, member w's waves
+// striding over the blocks.  Per block a wave loads the labels (kLB
+// coalesced loads in flight), keeps the rows whose label lies in range r
+// (ballots, compacted through LDS), and adds them into LDS with G lanes per
+// row and U rows per lane group in flight.  Sixteen waves share one copy of
+// the sums, so the copies' LDS still leaves room for 32 waves per CU.  The
+// range-0 workgroups also sum the cost and count the changed labels over
+// their blocks, so every row is counted once.
+constexpr int kLB = 4;       // 64-row label chunks per block
+constexpr int kLNT = 1024;   // threads per accumulation workgroup
+constexpr int kLNW = kLNT / 64;
+
+template <int FMT, int EPL>
+__global__ __launch_bounds__(kLNT) void lloyd_accum_kernel(LloydParams p) {
+  constexpr int U = EPL >= 16 ? 1 : 16 / EPL;  // rows per lane group in flight
+  extern __shared__ long long sh_acc[];        // [Kr * d] sums, then [Kr] int sizes
+  __shared__ double red[kLNW];
+  __shared__ unsigned int red_ch[kLNW];
+  __shared__ int s_pk[kLNW][kLB * 64];  // compacted rows: (label - j0) << 8 | row in block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int G = p.G;
+  const int sub = lane & (G - 1), rg = lane >> p.lgG;
+  const int rpw = 64 >> p.lgG;
+  const int r = blockIdx.x % p.R, w = blockIdx.x / p.R;
+  const int j0 = r * p.Kr, j1 = min(p.K, j0 + p.Kr);
+  const int nj = j1 - j0;
+  const int64_t kd = (int64_t)nj * p.d;
+  int* cnt = reinterpret_cast<int*>(sh_acc + (int64_t)p.Kr * p.d);
+  for (int64_t e = tid; e < kd; e += kLNT) sh_acc[e] = 0;
+  for (int j = tid; j < nj; j += kLNT) cnt[j] = 0;
+  __syncthreads();
   const int F = lloyd_F(p);
+  const bool tally = r == 0;
   double cost = 0.0;
   unsigned int changed = 0;
-  for (int64_t row = ((int64_t)blockIdx.x * 4 + wave) * rpw + rg; row < p.N; row += (int64_t)gridDim.x * 4 * rpw) {
-    const int lab = p.labels[row];
-    if ((unsigned)lab >= (unsigned)p.K) continue;  // label -1: a row with NaN (status set by the max pass)
-    long long* a = acc + (int64_t)lab * p.d;
-    for (int k = sub; k < p.d; k += p.G) {
-      const long long v = __float2ll_rn(ldexpf(lx<FMT>(p, row, k), F));
-      atomicAdd(reinterpret_cast<unsigned long long*>(a + k), (unsigned long long)v);
-    }
-    if (sub == 0) {
-      atomicAdd(cnt + lab, 1);
-      cost += (double)p.mind[row];
-      changed += p.prev ? (p.prev[row] != lab) : 1u;
-    }
-  }
-  if constexpr (LDS) {
-    __syncthreads();
-    for (int64_t e = tid; e < kd; e += 256) {
-      const long long v = sh_acc[e];
-      if (v) atomicAdd(reinterpret_cast<unsigned long long*>(p.acc + e), (unsigned long long)v);
-    }
-    for (int j = tid; j < p.K; j += 256)
-      if (cnt[j]) atomicAdd(p.cnt + j, cnt[j]);
-  }
-  cost = wave_sum(cost);
+  const int64_t nblocks = (p.N + kLB * 64 - 1) / (kLB * 64);
+  for (int64_t c = (int64_t)w * kLNW + wave; c < nblocks; c += (int64_t)p.W * kLNW) {
+    const int64_t base = c * (kLB * 64);
+    int lab[kLB];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) changed += __shfl_xor(changed, o, 64);
-  if (lane == 0) {
-    red[wave] = cost;
-    red_ch[wave] = changed;
+    for (int i = 0; i < kLB; ++i) {
+      const int64_t row = base + i * 64 + lane;
+      lab[i] = row < p.N ? p.labels[row] : -1;
+    }
+    int nm = 0;
+#pragma unroll
+    for (int i = 0; i < kLB; ++i) {
+      const int64_t row = base + i * 64 + lane;
+      // label -1 (a row with NaN; status set by the max pass) is in no range
+      if (tally && (unsigned)lab[i] < (unsigned)p.K) {
+        cost += (double)p.mind[row];
+        changed += p.prev ? (p.prev[row] != lab[i]) : 1u;
+      }
+      const bool in = lab[i] >= j0 && lab[i] < j1;
+      const unsigned long long m = __ballot(in);
+      if (in) s_pk[wave][nm + __popcll(m & ((1ull << lane) - 1ull))] = ((lab[i] - j0) << 8) | (i * 64 + lane);
+      nm += __popcll(m);
+    }
+    if (nm == 0) continue;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int q0 = 0; q0 < nm; q0 += rpw * U) {
+      float v[U][EPL];
+      int jr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int slot = q0 + u * rpw + rg;
+        const bool ok = slot < nm;
+        const int pk = ok ? s_pk[wave][slot] : -1;
+        const int64_t rr = base + (pk & 255);
+        jr[u] = ok ? (pk >> 8) : -1;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const int k = sub + G * e;
+          v[u][e] = (ok && k < p.d) ? lx<FMT>(p, rr, k) : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (jr[u] < 0) continue;
+        long long* a = sh_acc + (int64_t)jr[u] * p.d;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const int k = sub + G * e;
+          if (k < p.d)
+            atomicAdd(reinterpret_cast<unsigned long long*>(a + k),
+                      (unsigned long long)__float2ll_rn(ldexpf(v[u][e], F)));
+        }
+        if (sub == 0) atomicAdd(cnt + jr[u], 1);
+      }
+    }
+    // s_pk is rewritten by the next block
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
-  if (tid == 0) {
-    p.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-    const unsigned int c = red_ch[0] + red_ch[1] + red_ch[2] + red_ch[3];
-    if (p.changed && c) atomicAdd(p.changed, (unsigned long long)c);
+  long long* pa = p.pacc + ((int64_t)w * p.K + j0) * p.d;
+  for (int64_t e = tid; e < kd; e += kLNT) pa[e] = sh_acc[e];
+  int32_t* pc = p.pcnt + (int64_t)w * p.K + j0;
+  for (int j = tid; j < nj; j += kLNT) pc[j] = cnt[j];
+  if (tally) {
+    cost = wave_sum(cost);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) changed += __shfl_xor(changed, o, 64);
+    if (lane == 0) {
+      red[wave] = cost;
+      red_ch[wave] = changed;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sc = 0.0;
+      unsigned int cc = 0;
+      for (int i = 0; i < kLNW; ++i) {
+        sc += red[i];
+        cc += red_ch[i];
+      }
+      p.pcost[w] = sc;
+      p.pchg[w] = cc;
+    }
   }
 }
 
-// New centres (empty clusters keep theirs), sizes, and the cost as the sum
-// of the workgroup partials in a fixed order.
+// New centres from the W partials of every sum, added in member order
+// (empty clusters keep theirs); sizes; the cost as the sum of the range-0
+// partials in member order.
 __global__ __launch_bounds__(256) void lloyd_finalize_kernel(LloydParams p) {
   __shared__ double red[4];
+  __shared__ unsigned long long redc[4];
   const int F = lloyd_F(p);
   const int64_t kd = (int64_t)p.K * p.d;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e < kd) {
-    const int n = p.cnt[e / p.d];
-    if (n > 0) p.C[e] = (float)(ldexp((double)p.acc[e], -F) / (double)n);
+    const int64_t j = e / p.d;
+    long long s = 0;
+    int n = 0;
+#pragma unroll 8
+    for (int w = 0; w < p.W; ++w) {
+      s += p.pacc[(int64_t)w * kd + e];
+      n += p.pcnt[(int64_t)w * p.K + j];
+    }
+    if (n > 0) p.C[e] = (float)(ldexp((double)s, -F) / (double)n);
+    if (p.counts_out && e % p.d == 0) p.counts_out[j] = n;
   }
-  if (p.counts_out && e < p.K) p.counts_out[e] = p.cnt[e];
-  if (blockIdx.x == 0 && p.cost) {
-    const int per = (p.nparts + 255) / 256;
+  if (blockIdx.x == 0) {
+    const int per = (p.W + 255) / 256;
     const int b0 = threadIdx.x * per;
     double s = 0.0;
-    for (int i = b0; i < min(p.nparts, b0 + per); ++i) s += p.part[i];
+    unsigned long long c = 0;
+    for (int i = b0; i < min(p.W, b0 + per); ++i) {
+      s += p.pcost[i];
+      c += p.pchg[i];
+    }
     s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = s;
+      redc[threadIdx.x >> 6] = c;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) *p.cost = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0) {
+      if (p.cost) *p.cost = ((red[0] + red[1]) + red[2]) + red[3];
+      if (p.changed) *p.changed = ((redc[0] + redc[1]) + redc[2]) + redc[3];
+    }
   }
 }
 
@@ -190,14 +327,58 @@ __global__ __launch_bounds__(256) void lloyd_finalize_kernel(LloydParams p) {
 namespace {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kMaxParts = 4096;            // accumulation workgroups at most
-constexpr size_t kLdsBudget = 60 << 10;   // private sums in LDS up to this size
+constexpr int64_t kLdsBudget = 65536 - 17408;  // dynamic LDS of one workgroup (static LDS aside)
+constexpr int64_t kMaxAmaxWG = 2048;          // max-pass workgroups at most
+constexpr int64_t kTargetWG = 512;           // two workgroups per CU (LDS-bound)
+
+struct LloydPlan {
+  int G, lgG, R, Kr, W;
+  int epl;  // elements per lane per row: a power of two with G * epl >= d
+};
+
+LloydPlan lloyd_plan(int64_t N, int d, int K) {
+  LloydPlan P;
+  int lg = 0;
+  while ((1 << lg) < d && lg < 6) ++lg;
+  P.G = 1 << lg;
+  P.lgG = lg;
+  const int64_t per = (int64_t)d * 8 + 4;  // LDS bytes of one cluster
+  const int64_t kr_max = std::max<int64_t>(1, kLdsBudget / per);
+  P.R = (int)((K + kr_max - 1) / kr_max);
+  P.Kr = (K + P.R - 1) / P.R;
+  const int64_t steps = (N + kLNW * kLB * 64 - 1) / (kLNW * kLB * 64);  // one block per wave
+  P.W = (int)std::max<int64_t>(1, std::min<int64_t>(steps, kTargetWG / P.R));
+  P.epl = 1;
+  while (P.epl * P.G < d) P.epl <<= 1;
+  return P;
+}
+
+template <int FMT, int EPL>
+hipError_t launch_accum_e(const LloydParams& p, unsigned grid, size_t shmem, hipStream_t s) {
+  hipLaunchKernelGGL((lloyd_accum_kernel<FMT, EPL>), dim3(grid), dim3(kLNT), shmem, s, p);
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_accum(const LloydParams& p, int epl, unsigned grid, size_t shmem, hipStream_t s) {
+  switch (epl) {
+    case 1: return launch_accum_e<FMT, 1>(p, grid, shmem, s);
+    case 2: return launch_accum_e<FMT, 2>(p, grid, shmem, s);
+    case 4: return launch_accum_e<FMT, 4>(p, grid, shmem, s);
+    case 8: return launch_accum_e<FMT, 8>(p, grid, shmem, s);
+    case 16: return launch_accum_e<FMT, 16>(p, grid, shmem, s);
+    case 32: return launch_accum_e<FMT, 32>(p, grid, shmem, s);
+    case 64: return launch_accum_e<FMT, 64>(p, grid, shmem, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 struct LloydLayout {
-  size_t assign, mind, labels, acc, cnt, part, changed, total;
+  size_t assign, mind, labels, pacc, pcnt, pcost, pchg, pamax, changed, total;
 };
 
 LloydLayout lloyd_layout(int64_t N, int d, int K, int dtype) {
+  const LloydPlan P = lloyd_plan(N, d, K);
   LloydLayout L;
   size_t off = sizeof(LloydCtl);
   L.assign = off;
@@ -206,25 +387,20 @@ LloydLayout lloyd_layout(int64_t N, int d, int K, int dtype) {
   off += a256(sizeof(float) * (size_t)N);
   L.labels = off;
   off += a256(sizeof(int32_t) * (size_t)N);
-  L.acc = off;
-  off += a256(sizeof(long long) * (size_t)K * (size_t)d);
-  L.cnt = off;
-  off += a256(sizeof(int32_t) * (size_t)K);
-  L.part = off;
-  off += a256(sizeof(double) * kMaxParts);
+  L.pacc = off;
+  off += a256(sizeof(long long) * (size_t)P.W * (size_t)K * (size_t)d);
+  L.pcnt = off;
+  off += a256(sizeof(int32_t) * (size_t)P.W * (size_t)K);
+  L.pcost = off;
+  off += a256(sizeof(double) * (size_t)P.W);
+  L.pchg = off;
+  off += a256(sizeof(uint32_t) * (size_t)P.W);
+  L.pamax = off;
+  off += a256(sizeof(float) * kMaxAmaxWG);
   L.changed = off;
   off += 256;
   L.total = off;
   return L;
-}
-
-template <int FMT>
-hipError_t launch_accum(const LloydParams& p, bool lds, int grid, size_t shmem, hipStream_t s) {
-  if (lds)
-    hipLaunchKernelGGL((lloyd_accum_kernel<FMT, true>), dim3(grid), dim3(256), shmem, s, p);
-  else
-    hipLaunchKernelGGL((lloyd_accum_kernel<FMT, false>), dim3(grid), dim3(256), 0, s, p);
-  return hipGetLastError();
 }
 }  // namespace
 
@@ -235,6 +411,7 @@ int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d
                  size_t ws_bytes, hipStream_t stream) {
   const LloydLayout L = lloyd_layout(N, d, K, dtype);
   if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
+  const LloydPlan P = lloyd_plan(N, d, K);
   char* w = static_cast<char*>(ws);
   LloydParams p;
   p.X = X;
@@ -242,39 +419,43 @@ int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d
   p.N = N;
   p.d = d;
   p.K = K;
-  int lg = 0;
-  while ((1 << lg) < d && lg < 6) ++lg;
-  p.G = 1 << lg;
-  p.lgG = lg;
+  p.G = P.G;
+  p.lgG = P.lgG;
+  p.R = P.R;
+  p.Kr = P.Kr;
+  p.W = P.W;
   p.mind = reinterpret_cast<float*>(w + L.mind);
   p.C = C;
-  p.acc = reinterpret_cast<long long*>(w + L.acc);
-  p.cnt = reinterpret_cast<int32_t*>(w + L.cnt);
-  p.part = reinterpret_cast<double*>(w + L.part);
+  p.pacc = reinterpret_cast<long long*>(w + L.pacc);
+  p.pcnt = reinterpret_cast<int32_t*>(w + L.pcnt);
+  p.pcost = reinterpret_cast<double*>(w + L.pcost);
+  p.pchg = reinterpret_cast<uint32_t*>(w + L.pchg);
+  p.pamax = reinterpret_cast<float*>(w + L.pamax);
   p.lc = reinterpret_cast<LloydCtl*>(w);
-  p.counts_out = nullptr;
-
-  const size_t lds_bytes = sizeof(long long) * (size_t)K * d + sizeof(int) * (size_t)K;
-  const bool lds = lds_bytes <= kLdsBudget;
-  const int64_t rows_per_wg = 4 * (64 >> lg);
-  const int64_t want = (N + rows_per_wg - 1) / rows_per_wg;
-  const int grid = (int)std::min<int64_t>(want, lds ? 512 : kMaxParts);
-  p.nparts = grid;
-  const int64_t kd = (int64_t)K * d;
-  const unsigned fin_grid = (unsigned)((std::max<int64_t>(kd, K) + 255) / 256);
-
-  hipLaunchKernelGGL(lloyd_reset_kernel, dim3(1), dim3(1), 0, stream, p.lc);
   p.labels = nullptr;
   p.prev = nullptr;
   p.changed = nullptr;
   p.cost = nullptr;
-  const unsigned amax_grid = (unsigned)std::min<int64_t>(want, 2048);
+  p.counts_out = nullptr;
+
+  const size_t shmem = (size_t)P.Kr * ((size_t)d * 8 + 4);
+  const int64_t kd = (int64_t)K * d;
+  const unsigned fin_grid = (unsigned)((kd + 255) / 256);
+  const unsigned grid = (unsigned)(P.R * P.W);
+
+  hipLaunchKernelGGL(lloyd_reset_kernel, dim3(1), dim3(1), 0, stream, p.lc);
+  const int64_t rows_per_step = 4 * (64 >> P.lgG);
+  const unsigned amax_grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(dtype == KMPP_FP8_E4M3 ? (N + rows_per_step - 1) / rows_per_step
+                                                                              : (N * d / 4 + 1023) / 1024,
+                                                       kMaxAmaxWG));
   if (dtype == KMPP_F32)
     hipLaunchKernelGGL(lloyd_absmax_kernel<FMT_F32>, dim3(amax_grid), dim3(256), 0, stream, p);
   else if (dtype == KMPP_BF16)
     hipLaunchKernelGGL(lloyd_absmax_kernel<FMT_BF16>, dim3(amax_grid), dim3(256), 0, stream, p);
   else
     hipLaunchKernelGGL(lloyd_absmax_kernel<FMT_FP8>, dim3(amax_grid), dim3(256), 0, stream, p);
+  hipLaunchKernelGGL(lloyd_absmax_final_kernel, dim3(1), dim3(256), 0, stream, p, (int)amax_grid);
   if (hipGetLastError() != hipSuccess) return KMPP_E_HIP;
 
   int32_t* ws_labels = reinterpret_cast<int32_t*>(w + L.labels);
@@ -291,15 +472,13 @@ int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d
                             : reinterpret_cast<unsigned long long*>(w + L.changed);
     p.cost = out_cost ? out_cost + t : nullptr;
     p.counts_out = t == iters - 1 ? out_counts : nullptr;
-    hipLaunchKernelGGL(lloyd_clear_kernel, dim3((unsigned)std::min<int64_t>((kd + 255) / 256, 1024)), dim3(256), 0,
-                       stream, p);
     hipError_t e;
     if (dtype == KMPP_F32)
-      e = launch_accum<FMT_F32>(p, lds, grid, lds_bytes, stream);
+      e = launch_accum<FMT_F32>(p, P.epl, grid, shmem, stream);
     else if (dtype == KMPP_BF16)
-      e = launch_accum<FMT_BF16>(p, lds, grid, lds_bytes, stream);
+      e = launch_accum<FMT_BF16>(p, P.epl, grid, shmem, stream);
     else
-      e = launch_accum<FMT_FP8>(p, lds, grid, lds_bytes, stream);
+      e = launch_accum<FMT_FP8>(p, P.epl, grid, shmem, stream);
     if (e != hipSuccess) return KMPP_E_HIP;
     hipLaunchKernelGGL(lloyd_finalize_kernel, dim3(fin_grid), dim3(256), 0, stream, p);
     if (hipGetLastError() != hipSuccess) return KMPP_E_HIP;
