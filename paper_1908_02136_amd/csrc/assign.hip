@@ -45,6 +45,8 @@ struct AssignParams {
   int32_t d, K, Kp, dp; // dp = padded d: 4 * VPL * (steps per tile)
   int32_t nblk;         // number of 16-row blocks
   int32_t all_rows;     // recheck kernel: every row instead of the queue
+  float* Ct;            // [d, Kq] the centres transposed (zero past K)
+  int32_t Kq;           // K rounded up to 64
 };
 
 // ---- per-format row fragment handling
@@ -152,23 +154,49 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
 }
 
 // ---------------------------------------------------------------- main
+// Workgroup: 4 waves x RB blocks of 16 rows.  The packed centre tiles are
+// staged through LDS in chunks of TPC tiles, double-buffered: while the
+// waves run the products of chunk c from one buffer, the next chunk's global
+// loads are in flight and land in the other buffer at the end of the step,
+// so every centre byte comes from L2 once per workgroup and is read from
+// LDS by all four waves.
+//
+// The centres are the MFMA's first operand and the rows its second, so an
+// accumulator holds centres 4q..4q+3 of the tile (q = lane / 16) for row
+// lane % 16: each lane keeps one running top-2 per row block, and only the
+// four lane groups of a row are merged at the end.  Each chain starts from
+// the accumulator -||c_j||^2 / 2, so the running value is
+// t = <x, c_j> - ||c_j||^2 / 2 = -score / 2 and the per-pair work is the
+// top-2 update alone (largest t, ties to the smaller index).
 template <int FMT, int DQK, int RB>
 __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
   using F = Frag<FMT>;
-  constexpr int S = DQK;  // MFMA steps per centre tile (per product): dp / (4 * VPL)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr bool BF = FMT != FMT_F32;
+  constexpr int S = DQK;                                 // MFMA steps per centre tile (per product)
+  constexpr int TB = BF ? 2 * S * 64 * 16 : S * 64 * 4;  // bytes of one packed centre tile
+  constexpr int TPC = TB >= 16384 ? 1 : 16384 / TB;      // tiles per chunk
+  constexpr int CHB = TPC * TB;                          // bytes per chunk
+  constexpr int LPT = CHB / (256 * 16);                  // 16-byte loads per thread per chunk
+  static_assert(CHB % (256 * 16) == 0, "chunk is a whole number of 16-byte loads per thread");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, col = lane & 15;
   const int DQ = p.dp / 4;  // contraction elements per lane group
   const int Kt = p.Kp / 16;
-  __shared__ float s_gap[4][RB * 16];
-  __shared__ int s_best[4][RB * 16];
+  __shared__ uint4 sbuf[2][CHB / 16];
+  __shared__ uint4 scn[2][TPC * 4];  // ||c||^2 of the chunk's centres, 4 per entry
 
-  const int64_t blk0 = ((int64_t)blockIdx.x * 4 + wave) * RB;  // first 16-row block of this wave
-  if (blk0 >= p.nblk) return;                                  // whole wave idle (no barriers below)
+  // first 16-row block of this wave; waves past the last block compute on
+  // clamped rows and store nothing (they still take part in the barriers)
+  const int64_t blk0 = ((int64_t)blockIdx.x * 4 + wave) * RB;
 
-  // ---- row fragments (registers for the whole centre loop) and ||x||^2
+  // ---- row fragments (registers for the whole centre loop) and ||x||^2.
+  // A lane's fragment values are consecutive in the row, so rows whose
+  // width is a multiple of the fragment (4 FP32, 8 BF16/FP8 values) are read
+  // with one vector load per fragment.
   typename F::A a[RB][S];
   float xs[RB];  // partial sum of x^2 over this lane's quarter
+  const gptr<const char> xb = as_global(static_cast<const char*>(p.X));
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     int64_t row = (blk0 + rb) * 16 + col;
@@ -176,126 +204,181 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
     row = ok ? row : p.N - 1;
     float acc = 0.0f;
     if constexpr (FMT == FMT_F32) {
+      if (S % 4 == 0 && (p.d & 3) == 0) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int k = q * DQ + s;
-        const float v = (ok && k < p.d) ? static_cast<const float*>(p.X)[row * p.d + k] : 0.0f;
-        a[rb][s] = v;
-        acc = fmaf(v, v, acc);
+        for (int s4 = 0; s4 < S / 4; ++s4) {
+          const int k = q * DQ + 4 * s4;
+          const uint4 w = (ok && k < p.d) ? load_raw<16>(xb + (row * p.d + k) * 4) : make_uint4(0u, 0u, 0u, 0u);
+          const float v[4] = {__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w)};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            a[rb][4 * s4 + e] = v[e];
+            acc = fmaf(v[e], v[e], acc);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int k = q * DQ + s;
+          const float v = (ok && k < p.d) ? static_cast<const float*>(p.X)[row * p.d + k] : 0.0f;
+          a[rb][s] = v;
+          acc = fmaf(v, v, acc);
+        }
       }
     } else {
+      // FP8: the row's power-of-two scale is applied here; q * 2^e is exact
+      // in BF16 (3 mantissa bits, exponent within range)
       const float sc = (FMT == FMT_FP8) ? exp2i((int)p.xexp[row]) : 1.0f;
+      if ((p.d & 7) == 0) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
+        for (int s = 0; s < S; ++s) {
+          const int k = q * DQ + 8 * s;
+          const bool in = ok && k < p.d;
+          float xv[8];
+          if constexpr (FMT == FMT_BF16) {
+            const uint4 w = in ? load_raw<16>(xb + (row * p.d + k) * 2) : make_uint4(0u, 0u, 0u, 0u);
+            a[rb][s] = __builtin_bit_cast(v8bf, w);
+            decode<FMT_BF16, 16>(w, xv);
+          } else {
+            const uint2 w = in ? load_raw<8>(xb + (row * p.d + k)) : make_uint2(0u, 0u);
+            decode<FMT_FP8, 8>(w, xv);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = q * DQ + 8 * s + t;
-          uint16_t bits = 0;
-          float xv = 0.0f;
-          if (ok && k < p.d) {
-            if constexpr (FMT == FMT_BF16) {
-              bits = static_cast<const uint16_t*>(p.X)[row * p.d + k];
-              xv = __uint_as_float((uint32_t)bits << 16);
-            } else {
-              const uint8_t c8 = static_cast<const uint8_t*>(p.X)[row * p.d + k];
-              const float f = __builtin_amdgcn_cvt_f32_fp8((int)c8, 0);  // exact in BF16
-              bits = (uint16_t)(__float_as_uint(f) >> 16);
-              xv = f * sc;
+            for (int t = 0; t < 8; ++t) {
+              xv[t] *= sc;
+              a[rb][s][t] = bf_from_bits((uint16_t)(__float_as_uint(xv[t]) >> 16));
             }
           }
-          a[rb][s][t] = bf_from_bits(bits);
-          acc = fmaf(xv, xv, acc);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) acc = fmaf(xv[t], xv[t], acc);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int k = q * DQ + 8 * s + t;
+            float xv = 0.0f;
+            if (ok && k < p.d) {
+              if constexpr (FMT == FMT_BF16) {
+                xv = __uint_as_float((uint32_t) static_cast<const uint16_t*>(p.X)[row * p.d + k] << 16);
+              } else {
+                const uint8_t c8 = static_cast<const uint8_t*>(p.X)[row * p.d + k];
+                xv = __builtin_amdgcn_cvt_f32_fp8((int)c8, 0) * sc;
+              }
+            }
+            a[rb][s][t] = bf_from_bits((uint16_t)(__float_as_uint(xv) >> 16));
+            acc = fmaf(xv, xv, acc);
+          }
         }
       }
     }
     xs[rb] = acc;
   }
 
-  // ---- running top-2 per (row block, accumulator row)
-  float s1[RB][4], s2[RB][4];
-  int i1[RB][4];
+  // ---- running top-2 of t per row block (this lane's centres)
+  float m1[RB], m2[RB];
+  int i1[RB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      s1[rb][v] = INFINITY;
-      s2[rb][v] = INFINITY;
-      i1[rb][v] = INT_MAX;
-    }
+  for (int rb = 0; rb < RB; ++rb) {
+    m1[rb] = -INFINITY;
+    m2[rb] = -INFINITY;
+    i1[rb] = INT_MAX;
+  }
 
-  for (int jt = 0; jt < Kt; ++jt) {
-    v4f acc[RB];
+  // ---- centre chunks through LDS
+  const int nch = (Kt + TPC - 1) / TPC;
+  const gptr<const char> cp = as_global(static_cast<const char*>(p.Cp));
+  const gptr<const char> cnb = as_global(reinterpret_cast<const char*>(p.cn));
+  const int64_t cp_n = (int64_t)Kt * (TB / 16);  // 16-byte words of packed centres
+  uint4 pre[LPT];
+  uint4 pcn = make_uint4(0u, 0u, 0u, 0u);
+  auto gload = [&](int c) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) acc[rb] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (FMT == FMT_F32) {
-      const float* bp = static_cast<const float*>(p.Cp) + ((int64_t)jt * DQ) * 64 + lane;
+    for (int i = 0; i < LPT; ++i) {
+      const int64_t idx = (int64_t)c * (CHB / 16) + i * 256 + tid;
+      pre[i] = idx < cp_n ? load_raw<16>(cp + idx * 16) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    const int64_t ci = (int64_t)c * TPC * 4 + tid;  // 16-byte entry of cn
+    if (tid < TPC * 4) pcn = ci < (int64_t)Kt * 4 ? load_raw<16>(cnb + ci * 16) : make_uint4(0u, 0u, 0u, 0u);
+  };
+  auto sstore = [&](int b) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const float b = bp[s * 64];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b, acc[rb], 0, 0, 0);
-      }
-    } else {
-      const uint4* bp = static_cast<const uint4*>(p.Cp) + ((int64_t)jt * 2 * S) * 64 + lane;
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
+    for (int i = 0; i < LPT; ++i) sbuf[b][i * 256 + tid] = pre[i];
+    if (tid < TPC * 4) scn[b][tid] = pcn;
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) gload(c + 1);
+    const int tn = min(TPC, Kt - c * TPC);
+    // products of tile t into acc (the chain starts from -||c_j||^2 / 2)
+    auto products = [&](int t, v4f(&acc)[RB]) {
+      const int j0 = (c * TPC + t) * 16 + 4 * q;  // this lane's first centre of the tile
+      const uint4 c4 = scn[c & 1][t * 4 + q];     // ||c||^2 of centres j0..j0+3 (padding: 0)
+      const v4f init = v4f{j0 < p.K ? -0.5f * __uint_as_float(c4.x) : -INFINITY,
+                           j0 + 1 < p.K ? -0.5f * __uint_as_float(c4.y) : -INFINITY,
+                           j0 + 2 < p.K ? -0.5f * __uint_as_float(c4.z) : -INFINITY,
+                           j0 + 3 < p.K ? -0.5f * __uint_as_float(c4.w) : -INFINITY};
+      if constexpr (FMT == FMT_F32) {
+        const float* bp = reinterpret_cast<const float*>(&sbuf[c & 1][0]) + (t * S) * 64 + lane;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          const uint4 bw = bp[(h * S + s) * 64];
-          const v8bf b = __builtin_bit_cast(v8bf, bw);
+          const float cv = bp[s * 64];
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb][s], b, acc[rb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv, a[rb][s], s == 0 ? init : acc[rb], 0, 0, 0);
         }
-    }
-    const int j = jt * 16 + col;
-    const float cnj = j < p.K ? p.cn[j] : INFINITY;
-    if constexpr (FMT == FMT_FP8) {
-      // accumulator v holds row 16*blk + 4q + v: apply its scale
+      } else {
+        const uint4* bp = &sbuf[c & 1][(t * 2 * S) * 64 + lane];
+#pragma unroll
+        for (int hp = 0; hp < 2; ++hp)
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const v8bf cv = __builtin_bit_cast(v8bf, bp[(hp * S + s) * 64]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+              acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cv, a[rb][s], (hp == 0 && s == 0) ? init : acc[rb],
+                                                                0, 0, 0);
+          }
+      }
+    };
+    // running top-2 update with tile t's values
+    auto epilogue = [&](int t, const v4f(&acc)[RB]) {
+      const int j0 = (c * TPC + t) * 16 + 4 * q;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          int64_t row = (blk0 + rb) * 16 + 4 * q + v;
-          row = row < p.N ? row : p.N - 1;
-          acc[rb][v] *= exp2i((int)p.xexp[row]);
+          const float tv = acc[rb][v];
+          m2[rb] = fmaxf(m2[rb], fminf(m1[rb], tv));
+          i1[rb] = tv > m1[rb] ? j0 + v : i1[rb];
+          m1[rb] = fmaxf(m1[rb], tv);
         }
+    };
+    for (int t = 0; t < tn; ++t) {
+      v4f acc[RB];
+      products(t, acc);
+      epilogue(t, acc);
     }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float sc = fmaf(-2.0f, acc[rb][v], cnj);
-        if (sc < s1[rb][v]) {
-          s2[rb][v] = s1[rb][v];
-          s1[rb][v] = sc;
-          i1[rb][v] = j;
-        } else if (sc < s2[rb][v]) {
-          s2[rb][v] = sc;
-        }
-      }
+    if (c + 1 < nch) sstore((c + 1) & 1);
+    __syncthreads();
   }
 
-  // ---- merge across the 16 lanes that share rows (different centres)
+  // ---- scores s = -2 t (exact), merged over the four lane groups of a row
+  float s1[RB], s2[RB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < RB; ++rb) {
+    s1[rb] = -2.0f * m1[rb];
+    s2[rb] = -2.0f * m2[rb];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        const float t1 = __shfl_xor(s1[rb][v], o, 64);
-        const int j1 = __shfl_xor(i1[rb][v], o, 64);
-        const float t2 = __shfl_xor(s2[rb][v], o, 64);
-        top2_merge(s1[rb][v], i1[rb][v], s2[rb][v], t1, j1, t2);
-      }
-      if (col == 0) {
-        s_gap[wave][rb * 16 + 4 * q + v] = s2[rb][v] - s1[rb][v];
-        s_best[wave][rb * 16 + 4 * q + v] = i1[rb][v];
-      }
+    for (int o = 16; o < 64; o <<= 1) {
+      const float t1 = __shfl_xor(s1[rb], o, 64);
+      const int j1 = __shfl_xor(i1[rb], o, 64);
+      const float t2 = __shfl_xor(s2[rb], o, 64);
+      top2_merge(s1[rb], i1[rb], s2[rb], t1, j1, t2);
     }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
 
   // ---- per row (lanes of a row: same col, q = 0..3): ||x||, bound, direct
   // distance to the best centre over this lane's quarter
@@ -308,25 +391,39 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
     x2 += __shfl_xor(x2, 16, 64);
     x2 += __shfl_xor(x2, 32, 64);
     const int64_t row = (blk0 + rb) * 16 + col;
-    const int best = s_best[wave][rb * 16 + col];
-    const float gap = s_gap[wave][rb * 16 + col];
+    const int best = i1[rb];
+    const float gap = s2[rb] - s1[rb];
     const float xn = sqrtf(x2) * 1.0001f;
     const float mag = cmax2 + 2.0f * xn * cmax;
     const float unit =
         (FMT == FMT_F32) ? (float)(p.dp + 8) * 0x1p-24f : (float)(2 * p.dp + 8) * 0x1p-24f + 0x1p-16f;
     const float E = unit * mag * kGrowth;
     const bool sure = gap > 2.0f * E && best < p.K;
-    // direct distance to the best centre: this lane's quarter
+    // direct distance to the best centre over this lane's quarter: the
+    // row values are the fragments already in registers (exact), the
+    // centre's slice is read with all loads in flight
     float dd = 0.0f;
     const int bj = best < p.K ? best : 0;
-    if (row < p.N) {
-      for (int s = 0; s < DQ; ++s) {
-        const int k = q * DQ + s;
-        if (k < p.d) {
-          const float df = x_at<FMT>(p, row, k) - p.C[(int64_t)bj * p.d + k];
-          dd = fmaf(df, df, dd);
-        }
-      }
+    const float* crow = p.C + (int64_t)bj * p.d;
+    constexpr int QV = F::VPL * S;  // values per lane quarter (= DQ)
+    float cv[QV];
+#pragma unroll
+    for (int e = 0; e < QV; ++e) {
+      const int k = q * QV + e;
+      cv[e] = k < p.d ? crow[k] : 0.0f;
+    }
+    float xq[QV];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if constexpr (FMT == FMT_F32)
+        xq[s] = a[rb][s];
+      else
+        decode<FMT_BF16, 16>(__builtin_bit_cast(uint4, a[rb][s]), xq + 8 * s);
+    }
+#pragma unroll
+    for (int e = 0; e < QV; ++e) {
+      const float df = xq[e] - cv[e];
+      dd = (q * QV + e < p.d) ? fmaf(df, df, dd) : dd;
     }
     dd += __shfl_xor(dd, 16, 64);
     dd += __shfl_xor(dd, 32, 64);
@@ -343,42 +440,137 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
 }
 
 // ---------------------------------------------------------------- recheck
-// One wave per queued row: direct FP32 distances to every centre, lanes
-// split over centres, ties to the smallest index.
-template <int FMT>
+// Direct FP32 distances sum_k (x_k - c_jk)^2 (k in order) of the queued
+// rows (every row in all-rows mode) to every centre, ties to the smallest
+// index.  A wave takes kRR rows at once: lanes run over 64 centres at a
+// time, read coalesced from the transposed copy Ct[k][j], and every centre
+// value serves all kRR rows, whose values are the same for all lanes.
+constexpr int kRR = 8;
+
+__global__ __launch_bounds__(256) void assign_transpose_kernel(AssignParams p) {
+  const int64_t total = (int64_t)p.d * p.Kq;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t k = e / p.Kq, j = e % p.Kq;
+    p.Ct[e] = j < p.K ? p.C[j * p.d + k] : 0.0f;
+  }
+}
+
+// A workgroup takes kRR rows at once and its four waves split the centres
+// (64 per step, wave w from step w on).  XL: the rows' values are first
+// copied into LDS (interleaved by row, so one 16-byte read returns four
+// rows' value at one k); rows wider than kRecheckLdsD are read through the
+// scalar unit instead.  The waves' results are combined in wave order with
+// ties to the smaller index.
+constexpr int kRecheckLdsD = 256;
+
+template <int FMT, bool XL>
 __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ float4 sx[XL ? kRecheckLdsD * (kRR / 4) : 1];
+  __shared__ float s_b[4][kRR];
+  __shared__ int s_i[4][kRR];
   const int64_t n = p.all_rows ? p.N : (int64_t)p.ctl->nflag;
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < n; w += waves) {
-    const int64_t row = p.all_rows ? w : (int64_t)p.flags[w];
-    float best = INFINITY;
-    int bi = INT_MAX;
-    for (int j = lane; j < p.K; j += 64) {
-      float a = 0.0f;
+  const int64_t groups = (n + kRR - 1) / kRR;
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    int64_t rows[kRR];
+#pragma unroll
+    for (int r = 0; r < kRR; ++r) {
+      const int64_t i = min(g * kRR + r, n - 1);  // a short last group repeats its last row
+      rows[r] = p.all_rows ? i : (int64_t)p.flags[i];
+    }
+    if constexpr (XL) {
+      float* xw = reinterpret_cast<float*>(&sx[0]);
+      for (int e = tid; e < p.d * kRR; e += 256) {
+        const int k = e / kRR, r = e % kRR;
+        int64_t rr = rows[0];
+#pragma unroll
+        for (int q = 1; q < kRR; ++q) rr = r == q ? rows[q] : rr;
+        xw[e] = x_at<FMT>(p, rr, k);
+      }
+      __syncthreads();
+    }
+    float best[kRR];
+    int bi[kRR];
+#pragma unroll
+    for (int r = 0; r < kRR; ++r) {
+      best[r] = INFINITY;
+      bi[r] = INT_MAX;
+    }
+    for (int j0 = wave * 64; j0 < p.K; j0 += 256) {
+      const int j = j0 + lane;
+      const float* ct = p.Ct + j;
+      float acc[kRR];
+#pragma unroll
+      for (int r = 0; r < kRR; ++r) acc[r] = 0.0f;
+#pragma unroll 8
       for (int k = 0; k < p.d; ++k) {
-        const float df = x_at<FMT>(p, row, k) - p.C[(int64_t)j * p.d + k];
-        a = fmaf(df, df, a);
+        const float cv = ct[(int64_t)k * p.Kq];
+        float xv[kRR];
+        if constexpr (XL) {
+#pragma unroll
+          for (int r4 = 0; r4 < kRR / 4; ++r4) {
+            const float4 v = sx[k * (kRR / 4) + r4];
+            xv[4 * r4] = v.x;
+            xv[4 * r4 + 1] = v.y;
+            xv[4 * r4 + 2] = v.z;
+            xv[4 * r4 + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < kRR; ++r) xv[r] = x_at<FMT>(p, rows[r], k);
+        }
+#pragma unroll
+        for (int r = 0; r < kRR; ++r) {
+          const float df = xv[r] - cv;
+          acc[r] = fmaf(df, df, acc[r]);
+        }
       }
-      if (a < best) {
-        best = a;
-        bi = j;
-      }
+#pragma unroll
+      for (int r = 0; r < kRR; ++r)
+        if (j < p.K && acc[r] < best[r]) {
+          best[r] = acc[r];
+          bi[r] = j;
+        }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const float tb = __shfl_xor(best, o, 64);
-      const int ti = __shfl_xor(bi, o, 64);
-      if (tb < best || (tb == best && ti < bi)) {
-        best = tb;
-        bi = ti;
+    for (int r = 0; r < kRR; ++r) {
+      float b = best[r];
+      int ib = bi[r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const float tb = __shfl_xor(b, o, 64);
+        const int ti = __shfl_xor(ib, o, 64);
+        if (tb < b || (tb == b && ti < ib)) {
+          b = tb;
+          ib = ti;
+        }
+      }
+      if (lane == 0) {
+        s_b[wave][r] = b;
+        s_i[wave][r] = ib;
       }
     }
-    if (lane == 0) {
+    __syncthreads();
+    if (tid < kRR && g * kRR + tid < n) {
+      float b = s_b[0][tid];
+      int ib = s_i[0][tid];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const float tb = s_b[w][tid];
+        const int ti = s_i[w][tid];
+        if (tb < b || (tb == b && ti < ib)) {
+          b = tb;
+          ib = ti;
+        }
+      }
+      int64_t row = rows[0];
+#pragma unroll
+      for (int q = 1; q < kRR; ++q) row = tid == q ? rows[q] : row;
       // no comparable distance (NaN in the row or the centres): label -1
-      p.labels[row] = bi < p.K ? bi : -1;
-      if (p.mind) p.mind[row] = bi < p.K ? best : __builtin_nanf("");
+      p.labels[row] = ib < p.K ? ib : -1;
+      if (p.mind) p.mind[row] = ib < p.K ? b : __builtin_nanf("");
     }
+    __syncthreads();  // LDS is rewritten by the next group
   }
 }
 
@@ -394,8 +586,8 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 struct AssignLayout {
-  size_t cn, cmax, cp, flags, total;
-  int Kp, dp;
+  size_t cn, cmax, cp, ct, flags, total;
+  int Kp, dp, Kq;
 };
 
 // MFMA steps per centre tile for width d: a power of two so the padded row
@@ -420,6 +612,9 @@ AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   off += 256;
   L.cp = off;
   off += a256(dtype == KMPP_F32 ? sizeof(float) * (size_t)L.Kp * L.dp : sizeof(uint16_t) * 2 * (size_t)L.Kp * L.dp);
+  L.Kq = round_up(K, 64);
+  L.ct = off;
+  off += a256(sizeof(float) * (size_t)L.Kq * (size_t)d);
   L.flags = off;
   off += a256(sizeof(int32_t) * (size_t)N);
   L.total = off;
@@ -434,6 +629,15 @@ hipError_t launch_main(const AssignParams& p, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int FMT>
+void launch_recheck(const AssignParams& p, hipStream_t stream) {
+  const unsigned grid = 2048;
+  if (p.d <= kRecheckLdsD)
+    hipLaunchKernelGGL((assign_recheck_kernel<FMT, true>), dim3(grid), dim3(256), 0, stream, p);
+  else
+    hipLaunchKernelGGL((assign_recheck_kernel<FMT, false>), dim3(grid), dim3(256), 0, stream, p);
+}
+
 // RB row blocks per wave: fragment registers RB * steps * (1 or 4) <= 64
 template <int FMT>
 hipError_t dispatch_main(const AssignParams& p, int steps, hipStream_t stream) {
@@ -443,16 +647,16 @@ hipError_t dispatch_main(const AssignParams& p, int steps, hipStream_t stream) {
       case 2: return launch_main<FMT, 2, 4>(p, stream);
       case 4: return launch_main<FMT, 4, 4>(p, stream);
       case 8: return launch_main<FMT, 8, 4>(p, stream);
-      case 16: return launch_main<FMT, 16, 2>(p, stream);
-      case 32: return launch_main<FMT, 32, 1>(p, stream);
+      case 16: return launch_main<FMT, 16, 4>(p, stream);
+      case 32: return launch_main<FMT, 32, 2>(p, stream);
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (steps) {
       case 1: return launch_main<FMT, 1, 4>(p, stream);
       case 2: return launch_main<FMT, 2, 4>(p, stream);
-      case 4: return launch_main<FMT, 4, 2>(p, stream);
-      case 8: return launch_main<FMT, 8, 1>(p, stream);
+      case 4: return launch_main<FMT, 4, 4>(p, stream);
+      case 8: return launch_main<FMT, 8, 2>(p, stream);
       default: return hipErrorInvalidValue;
     }
   }
@@ -483,10 +687,13 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.Kp = L.Kp;
   p.dp = L.dp;
   p.nblk = (int)((N + 15) / 16);
+  p.Ct = reinterpret_cast<float*>(w + L.ct);
+  p.Kq = L.Kq;
 
   p.all_rows = 0;
 
   hipLaunchKernelGGL(assign_reset_kernel, dim3(1), dim3(1), 0, stream, p.ctl, p.cmax2);
+  hipLaunchKernelGGL(assign_transpose_kernel, dim3(256), dim3(256), 0, stream, p);
   const int steps = assign_steps(d, dtype);
   if (steps) {
     hipLaunchKernelGGL(assign_prep_kernel, dim3(256), dim3(256), 0, stream, p, dtype);
@@ -501,13 +708,12 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   } else {
     p.all_rows = 1;  // wider than the MFMA path: every row in the direct form
   }
-  const unsigned rb = 2048;
   if (dtype == KMPP_F32)
-    hipLaunchKernelGGL(assign_recheck_kernel<FMT_F32>, dim3(rb), dim3(256), 0, stream, p);
+    launch_recheck<FMT_F32>(p, stream);
   else if (dtype == KMPP_BF16)
-    hipLaunchKernelGGL(assign_recheck_kernel<FMT_BF16>, dim3(rb), dim3(256), 0, stream, p);
+    launch_recheck<FMT_BF16>(p, stream);
   else
-    hipLaunchKernelGGL(assign_recheck_kernel<FMT_FP8>, dim3(rb), dim3(256), 0, stream, p);
+    launch_recheck<FMT_FP8>(p, stream);
   return hipGetLastError() == hipSuccess ? KMPP_OK : KMPP_E_HIP;
 }
 
