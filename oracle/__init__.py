@@ -90,6 +90,11 @@ def lib():
         L.kmo_lloyd_update.restype = ctypes.c_int
         L.kmo_lloyd.argtypes = [P, i64, i32, i32, P, i32, P, P, P, i32]
         L.kmo_lloyd.restype = ctypes.c_int
+        L.kmo_uniform4.argtypes = [u64, u32, u32, u32, u32]
+        L.kmo_uniform4.restype = ctypes.c_double
+        L.kmo_kmpar.argtypes = [P, i64, i32, i32, u64, u32, i32, ctypes.c_double, i64, P, P, P, P, P, P, P, P, P,
+                                P, P, P, P, i32]
+        L.kmo_kmpar.restype = ctypes.c_int
         L.kmo_fp8_encode_bisect.argtypes = [ctypes.c_double]
         L.kmo_fp8_encode_bisect.restype = ctypes.c_uint8
         _lib = L
@@ -227,6 +232,50 @@ def lloyd(X, C0, iters: int, nthreads: int = 0):
     if st != OK:
         raise ValueError("oracle: invalid arguments")
     return C, lab, cost, ch
+
+
+# ---------------------------------------------------------------- k-means||
+def uniform4(seed: int, c0: int, c1: int, c2: int, c3: int) -> float:
+    """u in [0,1) from the Philox words of counter (c0, c1, c2, c3)."""
+    return lib().kmo_uniform4(seed, c0, c1, c2, c3)
+
+
+class KmparResult:
+    pass
+
+
+def kmpar(X, K: int, seed: int = 0, rounds: int = 5, ell: float | None = None, inst: int = 0,
+          cap: int | None = None, keep_D: bool = False, replay_cand=None, replay_end=None, replay_w=None,
+          replay_idx=None, nthreads: int = 0) -> KmparResult:
+    """k-means|| (Bahmani et al., Algorithm 2) in FP64: candidates, weights,
+    labels, and the K centres of the weighted k-means++ recluster."""
+    X = _f32(X)
+    N, d = X.shape
+    ell = float(2 * K) if ell is None else float(ell)
+    cap = N if cap is None else int(cap)
+    r = KmparResult()
+    r.cand = np.zeros(cap, dtype=np.int64)
+    nc = np.zeros(1, dtype=np.int64)
+    r.round_end = np.zeros(rounds + 1, dtype=np.int64)
+    r.weights = np.zeros(cap, dtype=np.int64)
+    r.labels = np.zeros(N, dtype=np.int32)
+    r.idx = np.zeros(K, dtype=np.int64)
+    r.rec = np.zeros((K, 8), dtype=np.float64)
+    r.phi = np.zeros(max(rounds, 1), dtype=np.float64)
+    r.Dr = np.zeros((max(rounds, 1), N), dtype=np.float64) if keep_D else None
+    conv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+    rc, re, rw, ri = conv(replay_cand), conv(replay_end), conv(replay_w), conv(replay_idx)
+    st = lib().kmo_kmpar(_ptr(X), N, d, K, seed, inst, rounds, ell, cap, _ptr(r.cand), _ptr(nc), _ptr(r.round_end),
+                         _ptr(r.weights), _ptr(r.labels), _ptr(r.idx), _ptr(r.rec), _ptr(r.phi), _ptr(r.Dr),
+                         _ptr(rc), _ptr(re), _ptr(rw), _ptr(ri), nthreads)
+    if st == E_INVALID:
+        raise ValueError("oracle: invalid arguments or candidate capacity exceeded")
+    r.status = st
+    r.ncand = int(nc[0])
+    r.cand = r.cand[:r.ncand]
+    mc = int(re[rounds]) if re is not None else r.ncand
+    r.weights = r.weights[:mc]
+    return r
 
 
 # ---------------------------------------------------------------- formats

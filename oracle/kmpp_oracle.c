@@ -552,3 +552,208 @@ int kmo_lloyd(const float* X, int64_t N, int32_t d, int32_t K, float* C, int32_t
   free(Cn);
   return KMO_OK;
 }
+
+/* ---- k-means|| (Bahmani, Moseley, Vattani, Kumar, Vassilvitskii, "Scalable
+ * K-Means++", PVLDB 5(7), 2012: Algorithm 2), the different initialisation
+ * the paper's introduction attributes to Bahmani et al.  Its steps, in
+ * order:
+ *   1. C = one point drawn uniformly at random;
+ *   2. `rounds` times: every point x joins C' independently with
+ *      probability min(1, ell * d^2(x, C) / phi(C)), phi(C) = sum_x d^2(x, C);
+ *      then C = C u C';
+ *   3. w_c = the number of points whose nearest candidate is c;
+ *   4. the weighted candidates are reclustered into K centres by weighted
+ *      k-means++: the first with probability proportional to w, each next
+ *      with probability proportional to w * d^2(c, chosen centres).
+ * Readings: the number of rounds is a parameter (the O(log psi) of the
+ * algorithm); candidates are kept in the order they join, within a round in
+ * point order; nearest-candidate ties go to the smaller candidate index;
+ * phi is the FP64 sum of D in point order; the random numbers are Philox
+ * words turned into u in [0,1) as in kmo_uniform with counters
+ *   first point               (0, inst, 0, 0)   (the k-means++ first seed)
+ *   point i in round r >= 1   (i, inst, r, 1)
+ *   recluster draw m >= 0     (m, inst, 0, 2);
+ * point i joins iff u < p (p computed in FP64 as ell * D_i / phi, capped at
+ * 1); a recluster draw inverts the weighted CDF over candidates in index
+ * order exactly like the k-means++ draw (first index whose inclusive prefix
+ * exceeds t = u * total; rounding fallback to the last positive entry;
+ * uniform candidate with a warning when the total is zero).
+ */
+static double kmo_u_ctr(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+  const uint32_t ctr[4] = {c0, c1, c2, c3};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t r[4];
+  kmo_philox4x32_10(ctr, key, r);
+  return (double)((uint64_t)(r[0] >> 5) * 67108864ull + (uint64_t)(r[1] >> 6)) / 9007199254740992.0;
+}
+
+double kmo_uniform4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+  return kmo_u_ctr(seed, c0, c1, c2, c3);
+}
+
+/*
+ * X [N*d] FP32 points; K centres; cap = capacity of the candidate list.
+ * Outputs: cand [cap] candidate point indices, *ncand, round_end [rounds+1]
+ * (candidates after the first point and after each round), weights [cap],
+ * labels [N] (nullable: nearest candidate of every point), out_idx [K]
+ * (point indices of the centres), rec [K*8] (per recluster draw: total, t,
+ * the prefix interval of the oracle's own index, the prefix interval of the
+ * replayed index, its weighted distance, u; row 0 for the first draw too),
+ * phi [rounds] (phi before each round) and Dr [rounds*N] (D before each
+ * round; nullable).
+ * Replay (all nullable): rp_cand/rp_end make every round start from the
+ * given candidates instead of the oracle's own; rp_w replaces the weights
+ * of the recluster; rp_idx makes every recluster draw start from the given
+ * earlier centres.  Returns KMO_OK, KMO_W_DEGENERATE, or a negative error
+ * (KMO_E_INVALID also when more than cap candidates would be needed).
+ */
+int kmo_kmpar(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, uint32_t inst, int32_t rounds,
+              double ell, int64_t cap, int64_t* cand, int64_t* ncand, int64_t* round_end, int64_t* weights,
+              int32_t* labels, int64_t* out_idx, double* rec, double* phi, double* Dr, const int64_t* rp_cand,
+              const int64_t* rp_end, const int64_t* rp_w, const int64_t* rp_idx, int32_t nthreads) {
+  if (!X || !cand || !ncand || !round_end || !weights || !out_idx || N < 1 || d < 1 || K < 1 || rounds < 0 ||
+      cap < 1 || !(ell > 0.0))
+    return KMO_E_INVALID;
+  const int nt = kmo_threads(nthreads);
+  int status = KMO_OK;
+  double* D = (double*)malloc(sizeof(double) * (size_t)N);
+  int32_t* lab = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  double* c = (double*)malloc(sizeof(double) * (size_t)d);
+  if (!D || !lab || !c) {
+    free(D);
+    free(lab);
+    free(c);
+    return KMO_E_INVALID;
+  }
+  /* 1. the first point */
+  int64_t m = 0;
+  cand[m++] = kmo_uniform_index(kmo_u_ctr(seed, 0u, inst, 0u, 0u), N);
+  const int64_t* C = rp_cand ? rp_cand : cand;
+  for (int64_t i = 0; i < N; ++i) {
+    D[i] = INFINITY;
+    lab[i] = -1;
+  }
+  round_end[0] = 1;
+  int64_t done = 0; /* candidates already folded into D */
+  for (int32_t r = 0; r <= rounds && status >= 0; ++r) {
+    /* fold the candidates that joined last into D and the labels */
+    const int64_t upto = r == 0 ? 1 : (rp_end ? rp_end[r] : round_end[r]);
+    for (int64_t j = done; j < upto; ++j) {
+      for (int32_t q = 0; q < d; ++q) c[q] = (double)X[C[j] * (int64_t)d + q];
+#pragma omp parallel for schedule(static) num_threads(nt)
+      for (int64_t i = 0; i < N; ++i) {
+        const double v = kmo_sqdist(X + i * (int64_t)d, c, d);
+        if (v < D[i]) {
+          D[i] = v;
+          lab[i] = (int32_t)j;
+        }
+      }
+    }
+    done = upto;
+    if (r == rounds) break;
+    /* 2. one round of independent draws */
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) s += D[i];
+    if (phi) phi[r] = s;
+    if (Dr) memcpy(Dr + (int64_t)r * N, D, sizeof(double) * (size_t)N);
+    if (!isfinite(s)) {
+      status = KMO_E_NONFINITE;
+      break;
+    }
+    const int64_t before = m;
+    for (int64_t i = 0; i < N && status >= 0; ++i) {
+      double p = s > 0.0 ? ell * D[i] / s : 0.0;
+      if (p > 1.0) p = 1.0;
+      if (kmo_u_ctr(seed, (uint32_t)i, inst, (uint32_t)(r + 1), 1u) < p) {
+        if (m >= cap) {
+          status = KMO_E_INVALID;
+          break;
+        }
+        cand[m++] = i;
+      }
+    }
+    (void)before;
+    round_end[r + 1] = m;
+  }
+  *ncand = m;
+  if (status < 0) {
+    free(D);
+    free(lab);
+    free(c);
+    return status;
+  }
+  /* 3. weights: points per nearest candidate (of the candidates in use) */
+  const int64_t mc = rp_end ? rp_end[rounds] : m;
+  for (int64_t j = 0; j < mc; ++j) weights[j] = 0;
+  for (int64_t i = 0; i < N; ++i) weights[lab[i]] += 1;
+  if (labels)
+    for (int64_t i = 0; i < N; ++i) labels[i] = lab[i];
+  const int64_t* W = rp_w ? rp_w : weights;
+  /* 4. weighted k-means++ over the candidates */
+  double* Dc = (double*)malloc(sizeof(double) * (size_t)mc);
+  double* S = (double*)malloc(sizeof(double) * (size_t)mc);
+  for (int64_t j = 0; j < mc; ++j) Dc[j] = INFINITY;
+  for (int32_t k = 0; k < K; ++k) {
+    /* weights of this draw: w (first) or w * Dc */
+    double acc = 0.0;
+    for (int64_t j = 0; j < mc; ++j) {
+      const double v = k == 0 ? (double)W[j] : (double)W[j] * Dc[j];
+      acc += v;
+      S[j] = acc;
+    }
+    const double T = acc;
+    const double u = kmo_u_ctr(seed, (uint32_t)k, inst, 0u, 2u);
+    int64_t g;
+    double* rr = rec ? rec + (int64_t)k * 8 : NULL;
+    if (!isfinite(T)) {
+      status = KMO_E_NONFINITE;
+      break;
+    }
+    volatile double tv = u * T;
+    const double t = tv;
+    if (T == 0.0) {
+      g = kmo_uniform_index(u, mc);
+      if (status == KMO_OK) status = KMO_W_DEGENERATE;
+    } else {
+      g = kmo_upper_bound(S, mc, t);
+      if (g >= mc) {
+        g = mc - 1;
+        while (g > 0 && S[g] == (g > 0 ? S[g - 1] : 0.0)) --g;
+      }
+    }
+    out_idx[k] = C[g];
+    const int64_t gr = rp_idx ? -1 : g; /* replayed candidate position, found below */
+    int64_t gp = gr;
+    if (rp_idx) {
+      for (int64_t j = 0; j < mc; ++j)
+        if (C[j] == rp_idx[k]) {
+          gp = j;
+          break;
+        }
+      if (gp < 0) gp = g;
+    }
+    if (rr) {
+      rr[0] = T;
+      rr[1] = t;
+      rr[2] = g > 0 ? S[g - 1] : 0.0;
+      rr[3] = S[g];
+      rr[4] = gp > 0 ? S[gp - 1] : 0.0;
+      rr[5] = S[gp];
+      rr[6] = k == 0 ? (double)W[gp] : (double)W[gp] * Dc[gp];
+      rr[7] = u;
+    }
+    /* the chosen centre (replayed if given) updates the candidates' D */
+    const int64_t cj = gp;
+    for (int32_t q = 0; q < d; ++q) c[q] = (double)X[C[cj] * (int64_t)d + q];
+    for (int64_t j = 0; j < mc; ++j) {
+      const double v = kmo_sqdist(X + C[j] * (int64_t)d, c, d);
+      if (v < Dc[j]) Dc[j] = v;
+    }
+  }
+  free(Dc);
+  free(S);
+  free(D);
+  free(lab);
+  free(c);
+  return status;
+}
