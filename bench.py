@@ -21,6 +21,8 @@ seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
                 them
   lloyd         Lloyd iterations after seeding (per-iteration time, the
                 centre update alone); --no-lloyd skips them
+  kmeans_parallel  k-means|| (Bahmani et al.) against k-means++ on the same
+                rows: time and cost of the K centres; --no-kmpar skips it
   memory_spaces the paper's memory-space comparison (Section II, Figs. 2c
                 and 3c) on this chip: every row path (cached, non-temporal,
                 buffer descriptor) x centre source (LDS, scalar, global) on
@@ -302,6 +304,41 @@ def lloyd_iterations(kl, name, w, iters=5, reps=2, dtype=0):
     return res
 
 
+def kmeans_parallel(kl, name, w, rounds=5, reps=2):
+    """k-means|| (Bahmani et al.) against k-means++ on the same rows: time,
+    candidates, and the cost sum_i min_j ||x_i - c_j||^2 of the K centres."""
+    X, N, d, K = w.X, w.N, w.d, w.K
+    ell = 2.0 * K
+
+    def cost(C):
+        _, mind, _ = kl.kmpp_assign(X, C)
+        return float(mind.double().sum().item())
+
+    out = {}
+
+    def run_par():
+        out["p"] = kl.kmpp_seed_parallel(X, K, 0, rounds=rounds, ell=ell)
+
+    def run_pp():
+        out["s"] = kl.kmpp_seed(X, K, 0)
+
+    run_par()
+    run_pp()
+    torch.cuda.synchronize()
+    ms_par = time_events(run_par, reps)
+    ms_pp = time_events(run_pp, reps)
+    idx, C, cand, rend, wts, lab, ws = out["p"]
+    st = kl.kmpp_status(ws)
+    ncand = int(rend[-1].item())
+    phi_par, phi_pp = cost(C), cost(out["s"][1])
+    res = {"workload": f"{name} N={N} d={d} K={K}", "rounds": rounds, "ell": ell, "candidates": ncand,
+           "kmeans_parallel_ms": ms_par, "kmeanspp_ms": ms_pp, "speedup_vs_kmeanspp": ms_pp / ms_par,
+           "cost_ratio_vs_kmeanspp": phi_par / phi_pp, "status": st}
+    _log(f"  k-means|| {res['workload']}: {ms_par:.2f} ms ({ncand} candidates) vs k-means++ {ms_pp:.2f} ms; "
+         f"cost ratio {phi_par / phi_pp:.4f}, status {st}")
+    return res
+
+
 def memory_spaces(kl, reps=3):
     """The paper's memory-space experiment (Section II; Figs. 2c, 3c) on this
     chip: every row path x centre source at one launch schedule, on the
@@ -352,6 +389,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched forms")
     ap.add_argument("--no-spaces", action="store_true", help="skip the memory-space comparison")
     ap.add_argument("--no-lloyd", action="store_true", help="skip the Lloyd iterations")
+    ap.add_argument("--no-kmpar", action="store_true", help="skip the k-means|| comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
@@ -451,6 +489,16 @@ def main():
         wu = kmpp_synth.unitsphere(device="cuda")
         res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3))
         res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3, dtype=kl.KMPP_BF16))
+        del wu
+        torch.cuda.empty_cache()
+    if not args.no_kmpar:
+        res["kmeans_parallel"] = [kmeans_parallel(kl, "plain", w)]
+        for nm in ("paper_k", "paper_n"):
+            wp = kmpp_synth.paper_shape(nm, device="cuda")
+            res["kmeans_parallel"].append(kmeans_parallel(kl, nm, wp))
+            del wp
+        wu = kmpp_synth.unitsphere(device="cuda")
+        res["kmeans_parallel"].append(kmeans_parallel(kl, "unitsphere", wu, reps=1))
         del wu
         torch.cuda.empty_cache()
     if not args.no_spaces:

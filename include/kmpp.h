@@ -157,6 +157,48 @@ int kmpp_assign(const void* X, const int8_t* X_exp, int32_t dtype, const float* 
                 void* stream);
 
 /*
+ * k-means|| initialisation (Bahmani, Moseley, Vattani, Kumar, Vassilvitskii,
+ * "Scalable K-Means++", PVLDB 2012, Algorithm 2), the different
+ * initialisation the paper's introduction attributes to Bahmani et al.
+ * A uniform first point; `rounds` rounds in which every point joins the
+ * candidate list independently with probability min(1, ell * D / phi)
+ * (D: squared distance to the nearest candidate, phi = sum D in FP64);
+ * candidate weights = points whose nearest candidate it is (ties to the
+ * smaller candidate index); then weighted k-means++ over the candidates
+ * (first centre proportional to w, then to w * D) gives the K centres.
+ * Philox4x32-10 keyed by `seed`, counters (0, instance, 0, 0) for the
+ * first point, (i, instance, r, 1) for point i in round r = 1..rounds and
+ * (m, instance, 0, 2) for the m-th recluster draw.
+ *
+ * X             FP32 [N, d], 16-byte aligned, d <= KMPP_MAX_D, N <= 2^31 - 1
+ * rounds        0..64; ell > 0 (typically 2K)
+ * out_centers   FP32 [K, d]: the chosen points, in draw order (required)
+ * out_idx       int64 [K] or NULL: their point indices
+ * out_cand      int64 [cap] or NULL: the candidates' point indices, in the
+ *               order they joined (within a round in point order);
+ *               cap = kmpp_seed_parallel_capacity(N, rounds, ell)
+ *               = min(N, 1 + rounds * (3 ceil(ell) + 64))
+ * out_round_end int32 [rounds + 1] or NULL: list length after the first
+ *               point and after each round
+ * out_weights   int32 [cap] or NULL: candidate weights (the first
+ *               round_end[rounds] entries are valid)
+ * out_labels    int32 [N] or NULL: every point's nearest candidate
+ * Device status (kmpp_status): KMPP_W_DEGENERATE when a recluster draw found
+ * every weighted distance zero (fewer than K distinct candidates),
+ * KMPP_E_NONFINITE for NaN/Inf, KMPP_E_WORKSPACE when more than cap points
+ * joined (the list is cut at cap; vanishingly unlikely: a round's expected
+ * number of joiners is at most ell).
+ * Synchronises `stream` once per round (the host reads the list length to
+ * size the next round's assignment), so it cannot be captured in a graph.
+ */
+int32_t kmpp_seed_parallel_capacity(int64_t N, int32_t rounds, double ell);
+size_t kmpp_seed_parallel_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t rounds, double ell);
+int kmpp_seed_parallel(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, int32_t rounds, double ell,
+                       uint32_t instance, float* out_centers, int64_t* out_idx, int64_t* out_cand,
+                       int32_t* out_round_end, int32_t* out_weights, int32_t* out_labels, void* workspace,
+                       size_t ws_bytes, void* stream);
+
+/*
  * Lloyd iterations after seeding.  Section II: once the initial centroids
  * are chosen, the clustering proceeds as standard k-means, whose result is
  * the partition O of Algorithm 1.  One iteration assigns every row to its

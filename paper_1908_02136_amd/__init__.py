@@ -32,7 +32,8 @@ MAX_D = 4096
 # Every symbol the header declares (checked by the test suite).
 SYMBOLS = [
     "kmpp_seed_workspace_bytes", "kmpp_seed", "kmpp_assign_workspace_bytes", "kmpp_assign", "kmpp_quantize",
-    "kmpp_lloyd_workspace_bytes", "kmpp_lloyd",
+    "kmpp_lloyd_workspace_bytes", "kmpp_lloyd", "kmpp_seed_parallel_capacity",
+    "kmpp_seed_parallel_workspace_bytes", "kmpp_seed_parallel",
     "kmpp_batched_workspace_bytes", "kmpp_seed_batched_prepare", "kmpp_seed_batched_launch",
     "kmpp_seed_batched", "kmpp_status", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
     "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_strerror", "kmpp_version",
@@ -82,6 +83,13 @@ def lib() -> ctypes.CDLL:
     L.kmpp_lloyd_workspace_bytes.restype = sz
     L.kmpp_lloyd.argtypes = [P, P, i32, i64, i32, i32, P, i32, P, P, P, P, P, sz, P]
     L.kmpp_lloyd.restype = ctypes.c_int
+    L.kmpp_seed_parallel_capacity.argtypes = [i64, i32, ctypes.c_double]
+    L.kmpp_seed_parallel_capacity.restype = i32
+    L.kmpp_seed_parallel_workspace_bytes.argtypes = [i64, i32, i32, i32, ctypes.c_double]
+    L.kmpp_seed_parallel_workspace_bytes.restype = sz
+    L.kmpp_seed_parallel.argtypes = [P, i64, i32, i32, u64, i32, ctypes.c_double, ctypes.c_uint32, P, P, P, P, P,
+                                     P, P, sz, P]
+    L.kmpp_seed_parallel.restype = ctypes.c_int
     L.kmpp_quantize.argtypes = [P, i64, i32, i32, P, P, P]
     L.kmpp_quantize.restype = ctypes.c_int
     L.kmpp_batched_workspace_bytes.argtypes = [ctypes.POINTER(Instance), i32]
@@ -217,6 +225,35 @@ def kmpp_assign(X: torch.Tensor, C: torch.Tensor, *, X_exp=None, dtype: int = KM
                            _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "kmpp_assign")
     return out_labels, out_mind, ws
+
+
+# ---------------------------------------------------------------- k-means||
+def kmpp_seed_parallel(X: torch.Tensor, K: int, seed: int = 0, *, rounds: int = 5, ell: float | None = None,
+                       instance: int = 0, out_centers=None, ws=None, stream=None):
+    """k-means|| seeding of the rows of X (FP32 [N, d], d <= 128).  Returns
+    (idx int64 [K], centers FP32 [K, d], cand int64 [cap], round_end int32
+    [rounds+1], weights int32 [cap], labels int32 [N], ws)."""
+    _require_cuda(X)
+    N, d = X.shape
+    ell = float(2 * K) if ell is None else float(ell)
+    dev = X.device
+    cap = int(lib().kmpp_seed_parallel_capacity(N, rounds, ell))
+    out_centers = torch.empty((K, d), dtype=torch.float32, device=dev) if out_centers is None else out_centers
+    idx = torch.empty(K, dtype=torch.int64, device=dev)
+    cand = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    rend = torch.empty(rounds + 1, dtype=torch.int32, device=dev)
+    w = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    lab = torch.empty(N, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(kmpp_seed_parallel_workspace_bytes(N, d, K, rounds, ell), dev)
+    rc = lib().kmpp_seed_parallel(_ptr(X), N, d, K, seed, rounds, ell, instance, _ptr(out_centers), _ptr(idx),
+                                  _ptr(cand), _ptr(rend), _ptr(w), _ptr(lab), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "kmpp_seed_parallel")
+    return idx, out_centers, cand, rend, w, lab, ws
+
+
+def kmpp_seed_parallel_workspace_bytes(N: int, d: int, K: int, rounds: int, ell: float) -> int:
+    return int(lib().kmpp_seed_parallel_workspace_bytes(N, d, K, rounds, ell))
 
 
 # ---------------------------------------------------------------- Lloyd

@@ -115,6 +115,67 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   return KMPP_OK;
 }
 
+size_t seed_workspace(int64_t N, int K) { return seed_layout(N, K).total; }
+
+int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t inst, uint32_t tag,
+             const int32_t* wts, float* out_centers, float* out_D, int64_t* out_idx, const void* Xq,
+             const int8_t* Xq_exp, int dtype, const kmpp_seed_opts* opts, void* workspace, size_t ws_bytes,
+             hipStream_t stream) {
+  const SeedLayout L = seed_layout(N, K);
+  if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
+  const SeedVariant* v = nullptr;
+  int rpt = 0, ntiles = 0;
+  const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles);
+  if (rc != KMPP_OK) return rc;
+  char* ws = static_cast<char*>(workspace);
+
+  SeedParams p;
+  p.xs = dtype == KMPP_F32 ? static_cast<const void*>(X) : Xq;
+  p.xexp = Xq_exp;
+  p.X = X;
+  p.centers = out_centers;
+  p.idx = out_idx ? out_idx : reinterpret_cast<int64_t*>(ws + L.idx);
+  p.D = out_D ? out_D : reinterpret_cast<float*>(ws + L.D);
+  p.tsum = reinterpret_cast<double*>(ws + L.tsum);
+  p.ctl = reinterpret_cast<Ctl*>(ws);
+  p.recheck = opts ? opts->out_recheck : nullptr;
+  p.N = N;
+  p.d = d;
+  p.K = K;
+  p.pass = 0;
+  p.rows_per_tile = rpt;
+  p.ntiles = ntiles;
+  p.inst = inst;
+  p.seed = seed;
+  p.wts = wts;
+  p.tag = tag;
+  hipEvent_t* ev = opts ? static_cast<hipEvent_t*>(opts->step_events) : nullptr;
+
+  void* args[] = {&p};
+  if (hipLaunchKernel(seed_init_fn(), dim3(1), dim3(256), args, 0, stream) != hipSuccess) return KMPP_E_HIP;
+  if (wts) {
+    // the first centre: a draw proportional to w (D := 1)
+    if (hipLaunchKernel(seed_wfirst_fn(), dim3((unsigned)ntiles), dim3(256), args, 0, stream) != hipSuccess ||
+        hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) != hipSuccess)
+      return KMPP_E_HIP;
+  }
+  const size_t shmem = sizeof(float) * (size_t)d;
+  for (int m = 1; m <= K; ++m) {
+    p.pass = m;
+    // with step events, the events are attached to the dispatch itself and
+    // track the kernel's own start and stop
+    const hipError_t le =
+        ev ? hipExtLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream,
+                                ev[2 * (m - 1)], ev[2 * (m - 1) + 1], 0)
+           : hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream);
+    if (le != hipSuccess) return KMPP_E_HIP;
+    if (m < K && hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
+                     hipSuccess)
+      return KMPP_E_HIP;
+  }
+  return KMPP_OK;
+}
+
 }  // namespace kmpp
 
 using namespace kmpp;
@@ -137,52 +198,32 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
     if (!Xq || !aligned(Xq, 16)) return KMPP_E_INVALID;
     if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
   }
-  const SeedLayout L = seed_layout(N, K);
-  if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
-  const SeedVariant* v = nullptr;
-  int rpt = 0, ntiles = 0;
-  const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles);
-  if (rc != KMPP_OK) return rc;
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  char* ws = static_cast<char*>(workspace);
+  return seed_run(X, N, d, K, seed, opts ? opts->instance : 0u, 0u, nullptr, out_centers, out_D, out_idx, Xq, Xq_exp,
+                  dtype, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream_));
+}
 
-  SeedParams p;
-  p.xs = dtype == KMPP_F32 ? static_cast<const void*>(X) : Xq;
-  p.xexp = Xq_exp;
-  p.X = X;
-  p.centers = out_centers;
-  p.idx = out_idx ? out_idx : reinterpret_cast<int64_t*>(ws + L.idx);
-  p.D = out_D ? out_D : reinterpret_cast<float*>(ws + L.D);
-  p.tsum = reinterpret_cast<double*>(ws + L.tsum);
-  p.ctl = reinterpret_cast<Ctl*>(ws);
-  p.recheck = opts ? opts->out_recheck : nullptr;
-  p.N = N;
-  p.d = d;
-  p.K = K;
-  p.pass = 0;
-  p.rows_per_tile = rpt;
-  p.ntiles = ntiles;
-  p.inst = opts ? opts->instance : 0u;
-  p.seed = seed;
-  hipEvent_t* ev = opts ? static_cast<hipEvent_t*>(opts->step_events) : nullptr;
+int32_t kmpp_seed_parallel_capacity(int64_t N, int32_t rounds, double ell) {
+  if (N < 1 || rounds < 0 || !(ell > 0.0)) return 0;
+  return kpar_capacity(N, rounds, ell);
+}
 
-  void* args[] = {&p};
-  if (hipLaunchKernel(seed_init_fn(), dim3(1), dim3(256), args, 0, stream) != hipSuccess) return KMPP_E_HIP;
-  const size_t shmem = sizeof(float) * (size_t)d;
-  for (int m = 1; m <= K; ++m) {
-    p.pass = m;
-    // with step events, the events are attached to the dispatch itself and
-    // track the kernel's own start and stop
-    const hipError_t le =
-        ev ? hipExtLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream,
-                                ev[2 * (m - 1)], ev[2 * (m - 1) + 1], 0)
-           : hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream);
-    if (le != hipSuccess) return KMPP_E_HIP;
-    if (m < K && hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
-                     hipSuccess)
-      return KMPP_E_HIP;
-  }
-  return KMPP_OK;
+size_t kmpp_seed_parallel_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t rounds, double ell) {
+  if (N < 1 || K < 1 || d < 1 || d > KMPP_MAX_D || rounds < 0 || rounds > 64 || !(ell > 0.0)) return 0;
+  return kpar_workspace(N, d, K, rounds, ell);
+}
+
+int kmpp_seed_parallel(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, int32_t rounds, double ell,
+                       uint32_t instance, float* out_centers, int64_t* out_idx, int64_t* out_cand,
+                       int32_t* out_round_end, int32_t* out_weights, int32_t* out_labels, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  if (!X || !out_centers || !workspace) return KMPP_E_INVALID;
+  if (N < 1 || K < 1 || N > INT32_MAX || d < 1 || d > KMPP_MAX_D || rounds < 0 || rounds > 64 || !(ell > 0.0) ||
+      ell > 1e12)
+    return KMPP_E_INVALID;
+  if (!aligned(X, 16) || !aligned(workspace, 256)) return KMPP_E_INVALID;
+  if (ws_bytes < kpar_workspace(N, d, K, rounds, ell)) return KMPP_E_WORKSPACE;
+  return launch_kpar(X, N, d, K, seed, rounds, ell, instance, out_centers, out_idx, out_cand, out_round_end,
+                     out_weights, out_labels, workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 size_t kmpp_lloyd_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype) {

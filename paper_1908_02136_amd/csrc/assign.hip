@@ -36,7 +36,7 @@ struct AssignParams {
   const float* C;       // [K, d] FP32
   const void* Cp;       // packed B fragments
   float* cn;            // [Kp] ||c_j||^2 (FP32, direct)
-  Ctl* ctl;             // nflag counter
+  Ctl* ctl;             // status
   int32_t* flags;       // [N] queued rows
   int32_t* labels;
   float* mind;
@@ -47,6 +47,11 @@ struct AssignParams {
   int32_t all_rows;     // recheck kernel: every row instead of the queue
   float* Ct;            // [d, Kq] the centres transposed (zero past K)
   int32_t Kq;           // K rounded up to 64
+  int32_t* fcnt;        // [nseg] rows queued by main-kernel workgroup b (segment b of flags)
+  int32_t* foff;        // [nseg] their offsets in the compacted queue
+  int32_t* cflags;      // [N] the compacted queue
+  int32_t seg;          // rows per segment (= rows per main-kernel workgroup)
+  int32_t nseg;         // segments (main-kernel workgroups)
 };
 
 // ---- per-format row fragment handling
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
   const int Kt = p.Kp / 16;
   __shared__ uint4 sbuf[2][CHB / 16];
   __shared__ uint4 scn[2][TPC * 4];  // ||c||^2 of the chunk's centres, 4 per entry
+  __shared__ int s_nf;               // rows this workgroup queued for the recheck
 
   // first 16-row block of this wave; waves past the last block compute on
   // clamped rows and store nothing (they still take part in the barriers)
@@ -308,6 +314,7 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
   };
   gload(0);
   sstore(0);
+  if (tid == 0) s_nf = 0;
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     if (c + 1 < nch) gload(c + 1);
@@ -427,16 +434,24 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
     }
     dd += __shfl_xor(dd, 16, 64);
     dd += __shfl_xor(dd, 32, 64);
-    if (q == 0 && row < p.N) {
-      if (sure) {
-        p.labels[row] = best;
-        if (p.mind) p.mind[row] = dd;
-      } else {
-        const uint32_t slot = atomicAdd(&p.ctl->nflag, 1u);
-        p.flags[slot] = (int32_t)row;
-      }
+    const bool mine = q == 0 && row < p.N;
+    if (mine && sure) {
+      p.labels[row] = best;
+      if (p.mind) p.mind[row] = dd;
+    }
+    // rows for the recheck go to this workgroup's segment of the queue (an
+    // LDS counter; no global atomics)
+    const bool flag = mine && !sure;
+    const unsigned long long fm = __ballot(flag);
+    if (fm) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s_nf, __popcll(fm));
+      base = __shfl(base, 0, 64);
+      if (flag) p.flags[(int64_t)blockIdx.x * p.seg + base + __popcll(fm & ((1ull << lane) - 1ull))] = (int32_t)row;
     }
   }
+  __syncthreads();
+  if (tid == 0) p.fcnt[blockIdx.x] = s_nf;
 }
 
 // ---------------------------------------------------------------- recheck
@@ -476,7 +491,7 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
 #pragma unroll
     for (int r = 0; r < kRR; ++r) {
       const int64_t i = min(g * kRR + r, n - 1);  // a short last group repeats its last row
-      rows[r] = p.all_rows ? i : (int64_t)p.flags[i];
+      rows[r] = p.all_rows ? i : (int64_t)p.cflags[i];
     }
     if constexpr (XL) {
       float* xw = reinterpret_cast<float*>(&sx[0]);
@@ -574,9 +589,45 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
   }
 }
 
+// The queue segments of the main kernel's workgroups, compacted in
+// workgroup order: one workgroup scans the counts (fixed order) ...
+__global__ __launch_bounds__(1024) void assign_qscan_kernel(AssignParams p) {
+  __shared__ int sh[1024];
+  const int per = (p.nseg + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  int s = 0;
+  for (int i = b0; i < min(p.nseg, b0 + per); ++i) s += p.fcnt[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+    p.ctl->nflag = (uint32_t)run;
+  }
+  __syncthreads();
+  int off = sh[threadIdx.x];
+  for (int i = b0; i < min(p.nseg, b0 + per); ++i) {
+    p.foff[i] = off;
+    off += p.fcnt[i];
+  }
+}
+
+// ... and every segment is copied to its offset.
+__global__ __launch_bounds__(256) void assign_qcopy_kernel(AssignParams p) {
+  for (int64_t sg = blockIdx.x; sg < p.nseg; sg += gridDim.x) {
+    const int n = p.fcnt[sg];
+    const int o = p.foff[sg];
+    for (int i = threadIdx.x; i < n; i += 256) p.cflags[o + i] = p.flags[sg * (int64_t)p.seg + i];
+  }
+}
+
 __global__ void assign_reset_kernel(Ctl* ctl, float* cmax2) {
   ctl->status = KMPP_OK;
-  ctl->nflag = 0u;
+
   *cmax2 = 0.0f;
 }
 
@@ -586,7 +637,7 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 struct AssignLayout {
-  size_t cn, cmax, cp, ct, flags, total;
+  size_t cn, cmax, cp, ct, flags, fcnt, foff, cflags, total;
   int Kp, dp, Kq;
 };
 
@@ -616,15 +667,23 @@ AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   L.ct = off;
   off += a256(sizeof(float) * (size_t)L.Kq * (size_t)d);
   L.flags = off;
+  off += a256(sizeof(int32_t) * (size_t)(N + 256));
+  L.fcnt = off;
+  off += a256(sizeof(int32_t) * (size_t)(N / 64 + 2));
+  L.foff = off;
+  off += a256(sizeof(int32_t) * (size_t)(N / 64 + 2));
+  L.cflags = off;
   off += a256(sizeof(int32_t) * (size_t)N);
   L.total = off;
   return L;
 }
 
 template <int FMT, int DQK, int RB>
-hipError_t launch_main(const AssignParams& p, hipStream_t stream) {
+hipError_t launch_main(AssignParams& p, hipStream_t stream) {
   const int64_t waves = (p.nblk + RB - 1) / RB;
   const int64_t blocks = (waves + 3) / 4;
+  p.seg = 4 * RB * 16;  // one recheck-queue segment per workgroup
+  p.nseg = (int)blocks;
   hipLaunchKernelGGL((assign_mfma_kernel<FMT, DQK, RB>), dim3((unsigned)blocks), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
@@ -640,7 +699,7 @@ void launch_recheck(const AssignParams& p, hipStream_t stream) {
 
 // RB row blocks per wave: fragment registers RB * steps * (1 or 4) <= 64
 template <int FMT>
-hipError_t dispatch_main(const AssignParams& p, int steps, hipStream_t stream) {
+hipError_t dispatch_main(AssignParams& p, int steps, hipStream_t stream) {
   if constexpr (FMT == FMT_F32) {
     switch (steps) {
       case 1: return launch_main<FMT, 1, 4>(p, stream);
@@ -689,6 +748,11 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.nblk = (int)((N + 15) / 16);
   p.Ct = reinterpret_cast<float*>(w + L.ct);
   p.Kq = L.Kq;
+  p.fcnt = reinterpret_cast<int32_t*>(w + L.fcnt);
+  p.foff = reinterpret_cast<int32_t*>(w + L.foff);
+  p.cflags = reinterpret_cast<int32_t*>(w + L.cflags);
+  p.seg = 256;  // all-rows mode; the main kernel's launch sets its own
+  p.nseg = (int)((N + 255) / 256);
 
   p.all_rows = 0;
 
@@ -705,6 +769,8 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
     else
       e = dispatch_main<FMT_FP8>(p, steps, stream);
     if (e != hipSuccess) return KMPP_E_HIP;
+    hipLaunchKernelGGL(assign_qscan_kernel, dim3(1), dim3(1024), 0, stream, p);
+    hipLaunchKernelGGL(assign_qcopy_kernel, dim3(1024), dim3(256), 0, stream, p);
   } else {
     p.all_rows = 1;  // wider than the MFMA path: every row in the direct form
   }

@@ -56,9 +56,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1
   return x;
 }
 
-// u in [0,1) with 53 random bits: counter (step, instance, 0, 0).
-__device__ __forceinline__ double draw_uniform(uint64_t seed, uint32_t step, uint32_t inst) {
-  const uint4 r = philox4x32_10(make_uint4(step, inst, 0u, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+// u in [0,1) with 53 random bits: counter (step, instance, 0, tag); tag 0
+// is the k-means++ stream, other tags separate other streams of a run.
+__device__ __forceinline__ double draw_uniform(uint64_t seed, uint32_t step, uint32_t inst, uint32_t tag = 0u) {
+  const uint4 r = philox4x32_10(make_uint4(step, inst, 0u, tag), (uint32_t)seed, (uint32_t)(seed >> 32));
   const uint64_t m = ((uint64_t)(r.x >> 5) << 26) | (uint64_t)(r.y >> 6);
   return (double)m * 0x1p-53;
 }

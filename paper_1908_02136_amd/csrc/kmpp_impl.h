@@ -32,6 +32,8 @@ struct SeedParams {
   int32_t ntiles;
   uint32_t inst;
   uint64_t seed;
+  const int32_t* wts;    // weighted seeding: row weights (draws proportional to w * D), or null
+  uint32_t tag;          // Philox counter word 3 of the draws (0: the k-means++ stream)
 };
 
 // One compiled seed-pass kernel.
@@ -49,12 +51,21 @@ struct SeedVariant {
 
 const std::vector<SeedVariant>& seed_variants();
 const void* seed_init_fn();
+const void* seed_wfirst_fn();
 const void* seed_draw_fn();
 int seed_draw_threads();
 
 // Maximum number of tiles of one pass; bounds the tile-sum scan of the draw
 // and the workspace.
 constexpr int64_t kMaxTiles = 8192;  // = draw threads (256) x tile sums per thread (32)
+
+// One k-means++ run (init, K passes, K-1 draws) on the stream; weighted when
+// wts is non-null (the first draw proportional to w, then to w * D).
+int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t inst, uint32_t tag,
+             const int32_t* wts, float* out_centers, float* out_D, int64_t* out_idx, const void* Xq,
+             const int8_t* Xq_exp, int dtype, const kmpp_seed_opts* opts, void* ws, size_t ws_bytes,
+             hipStream_t stream);
+size_t seed_workspace(int64_t N, int K);
 
 // Assignment
 struct AssignParams;
@@ -67,6 +78,13 @@ size_t lloyd_workspace(int64_t N, int d, int K, int dtype);
 int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d, int K, float* C, int iters,
                  int32_t* out_labels, double* out_cost, int64_t* out_changed, int32_t* out_counts, void* ws,
                  size_t ws_bytes, hipStream_t stream);
+
+// k-means||
+int kpar_capacity(int64_t N, int R, double ell);
+size_t kpar_workspace(int64_t N, int d, int K, int R, double ell);
+int launch_kpar(const float* X, int64_t N, int d, int K, uint64_t seed, int R, double ell, uint32_t inst,
+                float* out_centers, int64_t* out_idx, int64_t* out_cand, int32_t* out_round_end, int32_t* out_weights,
+                int32_t* out_labels, void* ws, size_t ws_bytes, hipStream_t stream);
 
 // Quantisers
 int launch_quantize(const float* X, int64_t N, int d, int dtype, void* Xq, int8_t* Xq_exp, hipStream_t stream);

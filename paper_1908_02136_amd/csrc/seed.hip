@@ -39,6 +39,24 @@ __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
   for (int j = threadIdx.x; j < p.d; j += blockDim.x) p.centers[j] = src[j];
 }
 
+// Weighted seeding, before the first draw: D := 1 for every row and the
+// tile sums := FP64 sums of the weights, so the draw kernel (pass 0) picks
+// the first centre with probability proportional to w.
+__global__ __launch_bounds__(256) void seed_wfirst_kernel(SeedParams p) {
+  __shared__ double red[4];
+  const int64_t t0 = (int64_t)blockIdx.x * p.rows_per_tile;
+  const int64_t t1 = min(p.N, t0 + (int64_t)p.rows_per_tile);
+  double acc = 0.0;
+  for (int64_t i = t0 + threadIdx.x; i < t1; i += 256) {
+    p.D[i] = 1.0f;
+    acc += (double)p.wts[i];
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) p.tsum[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // ---------------------------------------------------------------- S3-S5
 // Draw seed p.pass from the pass just finished, in one workgroup (the
 // kernel boundary makes every D and tile sum of the pass visible):
@@ -125,7 +143,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
   }
   const double2 sc = draw_scan(part, sh);
   const double T = sc.y;
-  const double u = draw_uniform(p.seed, (uint32_t)p.pass, p.inst);
+  const double u = draw_uniform(p.seed, (uint32_t)p.pass, p.inst, p.tag);
 
   int64_t seed_row;
   if (!isfinite(T)) {
@@ -161,37 +179,39 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
     const int64_t q0 = r0 + min(n, tid * per2);
     const int nq = max(0, min(per2, (int)(r1 - q0)));
     int found = NONE, lastrow = -1;
+    // a row's share: D, or w * D (FP64) for weighted seeding
+    auto share = [&](int64_t i, float dk) { return p.wts ? (double)dk * (double)p.wts[i] : (double)dk; };
     if (per2 <= kDrawRows) {
-      float dv[kDrawRows];
+      double dv[kDrawRows];
 #pragma unroll
-      for (int k = 0; k < kDrawRows; ++k) dv[k] = k < nq ? p.D[q0 + k] : 0.0f;
+      for (int k = 0; k < kDrawRows; ++k) dv[k] = k < nq ? share(q0 + k, p.D[q0 + k]) : 0.0;
       double part2 = 0.0;
 #pragma unroll
       for (int k = 0; k < kDrawRows; ++k) {
-        part2 += (double)dv[k];
-        if (dv[k] > 0.0f) lastrow = (int)(q0 - r0) + k;
+        part2 += dv[k];
+        if (dv[k] > 0.0) lastrow = (int)(q0 - r0) + k;
       }
       const double2 sc2 = draw_scan(part2, sh);
       if (inside) {
         double r = tlo + sc2.x;
 #pragma unroll
         for (int k = 0; k < kDrawRows; ++k) {
-          r += (double)dv[k];
+          r += dv[k];
           if (found == NONE && k < nq && r > t) found = (int)(q0 - r0) + k;
         }
       }
     } else {  // very large tiles: same steps, values reloaded
       double part2 = 0.0;
       for (int k = 0; k < nq; ++k) {
-        const float dk = p.D[q0 + k];
-        part2 += (double)dk;
-        if (dk > 0.0f) lastrow = (int)(q0 - r0) + k;
+        const double dk = share(q0 + k, p.D[q0 + k]);
+        part2 += dk;
+        if (dk > 0.0) lastrow = (int)(q0 - r0) + k;
       }
       const double2 sc2 = draw_scan(part2, sh);
       if (inside) {
         double r = tlo + sc2.x;
         for (int k = 0; k < nq && found == NONE; ++k) {
-          r += (double)p.D[q0 + k];
+          r += share(q0 + k, p.D[q0 + k]);
           if (r > t) found = (int)(q0 - r0) + k;
         }
       }
@@ -258,7 +278,9 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     __syncthreads();
     st.set_centre(cs, d);
   }
-  if (blockIdx.x == 0 && p.pass > 1)
+  // centre m-1 is stored by this pass (centre 0 by the init kernel, except
+  // for weighted seeding, whose first centre comes from a draw)
+  if (blockIdx.x == 0 && (p.pass > 1 || p.wts))
     for (int j = tid; j < d; j += NT) p.centers[(int64_t)(p.pass - 1) * d + j] = CS == CEN_LDS ? cs[j] : cg[j];
   st.set_rows(p.xs, t0, t1, d);
 
@@ -267,7 +289,7 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   for (int64_t base = t0 + (int64_t)st.wave * S::R; base < t1; base += (int64_t)NW * S::R)
     st.iter(p, base, t1, first, prev, [&](int64_t row, float dn) {
       D[row] = dn;
-      acc += (double)dn;
+      acc += p.wts ? (double)dn * (double)p.wts[row] : (double)dn;
     });
 
   acc = wave_sum(acc);
@@ -362,6 +384,7 @@ const std::vector<SeedVariant>& seed_variants() {
 }
 
 const void* seed_init_fn() { return reinterpret_cast<const void*>(&seed_init_kernel); }
+const void* seed_wfirst_fn() { return reinterpret_cast<const void*>(&seed_wfirst_kernel); }
 const void* seed_draw_fn() { return reinterpret_cast<const void*>(&seed_draw_kernel); }
 int seed_draw_threads() { return kDrawNT; }
 
