@@ -188,8 +188,8 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
       for (int it = 0; it < kBIT; ++it) {
         const int64_t base = wb + (int64_t)(blk * kBIT + it) * R;
         if (base < we)
-          st.iter(sp, base, we, first, -1, [&](int64_t row, float dn) {
-            D[row] = dn;
+          st.iter(sp, base, we, first, -1, [&](int64_t row, float dn, bool changed) {
+            if (changed) D[row] = dn;
             acc += (double)dn;
           });
       }

@@ -14,8 +14,8 @@
 // whole consecutive rows (1 KiB contiguous).  Each lane keeps the centre
 // slice of its chunks in registers and the row distance is reduced across
 // the G lanes with xor shuffles.  U loads per lane are issued before any is
-// consumed.  D is read and written once per row per pass, 64 rows per
-// coalesced access.
+// consumed.  D is read once per row per pass, 64 rows per coalesced
+// access, and written back only where it changed.
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 #include "stream.h"
@@ -287,8 +287,8 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   double acc = 0.0;
   float* D = p.D;
   for (int64_t base = t0 + (int64_t)st.wave * S::R; base < t1; base += (int64_t)NW * S::R)
-    st.iter(p, base, t1, first, prev, [&](int64_t row, float dn) {
-      D[row] = dn;
+    st.iter(p, base, t1, first, prev, [&](int64_t row, float dn, bool changed) {
+      if (changed) D[row] = dn;
       acc += p.wts ? (double)dn * (double)p.wts[row] : (double)dn;
     });
 

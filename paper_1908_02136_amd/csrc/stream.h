@@ -13,7 +13,7 @@ namespace kmpp {
 // registers, the row distance is reduced across the G lanes with xor
 // shuffles, and U loads per lane are issued before any is consumed.
 // iter() handles the R = U*64/G rows of one wave starting at `base` and
-// hands every row's new nearest distance to `sink(row, dnew)`; a row's
+// hands every row's new nearest distance to `sink(row, dnew, changed)`; a row's
 // arithmetic depends only on the template parameters, not on where the
 // rows (RL: ROW_CACHED, ROW_NONTEMPORAL or ROW_BUFFER) or the centre come
 // from.
@@ -173,7 +173,9 @@ struct Streamer {
       if (uu < U && row < r1) {
         float dn = first ? dv : fminf(b.dold[j], dv);
         if constexpr (FMT != FMT_F32) dn = (row == prev) ? 0.0f : dn;
-        sink(row, dn);
+        // most rows keep their nearest distance once a few seeds exist:
+        // `changed` lets the sink skip their store
+        sink(row, dn, first || !(dn == b.dold[j]));
       }
     }
   }
