@@ -156,7 +156,7 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   if (wts) {
     // the first centre: a draw proportional to w (D := 1)
     if (hipLaunchKernel(seed_wfirst_fn(), dim3((unsigned)ntiles), dim3(256), args, 0, stream) != hipSuccess ||
-        hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) != hipSuccess)
+        hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) != hipSuccess)
       return KMPP_E_HIP;
   }
   const size_t shmem = sizeof(float) * (size_t)d;
@@ -169,7 +169,7 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
                                 ev[2 * (m - 1)], ev[2 * (m - 1) + 1], 0)
            : hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream);
     if (le != hipSuccess) return KMPP_E_HIP;
-    if (m < K && hipLaunchKernel(seed_draw_fn(), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
+    if (m < K && hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
                      hipSuccess)
       return KMPP_E_HIP;
   }

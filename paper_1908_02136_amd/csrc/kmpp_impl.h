@@ -52,7 +52,7 @@ struct SeedVariant {
 const std::vector<SeedVariant>& seed_variants();
 const void* seed_init_fn();
 const void* seed_wfirst_fn();
-const void* seed_draw_fn();
+const void* seed_draw_fn(bool weighted);
 int seed_draw_threads();
 
 // Maximum number of tiles of one pass; bounds the tile-sum scan of the draw

@@ -16,6 +16,8 @@
 // the G lanes with xor shuffles.  U loads per lane are issued before any is
 // consumed.  D is read once per row per pass, 64 rows per coalesced
 // access, and written back only where it changed.
+#include <type_traits>
+
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 #include "stream.h"
@@ -117,6 +119,7 @@ __device__ __forceinline__ int2 draw_minmax(int a, int b, int2* sh) {
   return r;
 }
 
+template <bool WEIGHTED>
 __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
   constexpr int NT = kDrawNT;
   constexpr int NW = NT / 64;
@@ -180,30 +183,36 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
     const int nq = max(0, min(per2, (int)(r1 - q0)));
     int found = NONE, lastrow = -1;
     // a row's share: D, or w * D (FP64) for weighted seeding
-    auto share = [&](int64_t i, float dk) { return p.wts ? (double)dk * (double)p.wts[i] : (double)dk; };
+    using Share = typename std::conditional<WEIGHTED, double, float>::type;
+    auto share = [&](int64_t i, float dk) -> Share {
+      if constexpr (WEIGHTED)
+        return (double)dk * (double)p.wts[i];
+      else
+        return dk;
+    };
     if (per2 <= kDrawRows) {
-      double dv[kDrawRows];
+      Share dv[kDrawRows];
 #pragma unroll
-      for (int k = 0; k < kDrawRows; ++k) dv[k] = k < nq ? share(q0 + k, p.D[q0 + k]) : 0.0;
+      for (int k = 0; k < kDrawRows; ++k) dv[k] = k < nq ? share(q0 + k, p.D[q0 + k]) : Share(0);
       double part2 = 0.0;
 #pragma unroll
       for (int k = 0; k < kDrawRows; ++k) {
-        part2 += dv[k];
-        if (dv[k] > 0.0) lastrow = (int)(q0 - r0) + k;
+        part2 += (double)dv[k];
+        if (dv[k] > Share(0)) lastrow = (int)(q0 - r0) + k;
       }
       const double2 sc2 = draw_scan(part2, sh);
       if (inside) {
         double r = tlo + sc2.x;
 #pragma unroll
         for (int k = 0; k < kDrawRows; ++k) {
-          r += dv[k];
+          r += (double)dv[k];
           if (found == NONE && k < nq && r > t) found = (int)(q0 - r0) + k;
         }
       }
     } else {  // very large tiles: same steps, values reloaded
       double part2 = 0.0;
       for (int k = 0; k < nq; ++k) {
-        const double dk = share(q0 + k, p.D[q0 + k]);
+        const double dk = (double)share(q0 + k, p.D[q0 + k]);
         part2 += dk;
         if (dk > 0.0) lastrow = (int)(q0 - r0) + k;
       }
@@ -211,7 +220,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
       if (inside) {
         double r = tlo + sc2.x;
         for (int k = 0; k < nq && found == NONE; ++k) {
-          r += share(q0 + k, p.D[q0 + k]);
+          r += (double)share(q0 + k, p.D[q0 + k]);
           if (r > t) found = (int)(q0 - r0) + k;
         }
       }
@@ -385,7 +394,10 @@ const std::vector<SeedVariant>& seed_variants() {
 
 const void* seed_init_fn() { return reinterpret_cast<const void*>(&seed_init_kernel); }
 const void* seed_wfirst_fn() { return reinterpret_cast<const void*>(&seed_wfirst_kernel); }
-const void* seed_draw_fn() { return reinterpret_cast<const void*>(&seed_draw_kernel); }
+const void* seed_draw_fn(bool weighted) {
+  return weighted ? reinterpret_cast<const void*>(&seed_draw_kernel<true>)
+                  : reinterpret_cast<const void*>(&seed_draw_kernel<false>);
+}
 int seed_draw_threads() { return kDrawNT; }
 
 }  // namespace kmpp
