@@ -1,6 +1,7 @@
 /*
- * kmpp.h -- C ABI of libkmpp: k-means++ seeding (D^2 sampling) and
- * nearest-seed assignment on AMD Instinct MI355X (gfx950).
+ * kmpp.h -- C ABI of libkmpp: k-means++ seeding (D^2 sampling), the
+ * nearest-seed assignment, and the steps around them (Lloyd iterations,
+ * k-means|| seeding, a batched form) on AMD Instinct MI355X (gfx950).
  *
  * The method is the one of "Parallelization of Kmeans++ using CUDA"
  * (Heydarpour Shahrezaei and Tavoli, arXiv 1908.02136), Section II:
@@ -25,11 +26,13 @@
  * Conventions for every entry point:
  *   - all array pointers are DEVICE pointers unless stated otherwise; rows
  *     are contiguous and row-major; X's base must be 16-byte aligned;
- *   - `stream` is a hipStream_t (NULL = the null stream); work is enqueued
- *     asynchronously on it and the call returns without synchronising;
+ *   - `stream` is a hipStream_t (NULL = the null stream) on which the work
+ *     is enqueued;
  *   - the caller owns every buffer, including the workspace, whose size the
  *     matching *_workspace_bytes function gives; the library allocates no
  *     device memory in any entry point;
+ *   - work is enqueued without synchronising, except kmpp_status,
+ *     kmpp_seed_batched_prepare and kmpp_seed_parallel (stated below);
  *   - arguments are validated before anything is enqueued: a negative
  *     return means nothing was launched; KMPP_E_HIP means a launch failed;
  *   - conditions found on the device (non-finite or zero sum of D, an
@@ -273,9 +276,10 @@ int kmpp_seed_batched(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, 
                       size_t ws_bytes, void* stream);
 
 /* Status word written by the device (KMPP_OK, KMPP_W_DEGENERATE,
- * KMPP_E_NONFINITE, KMPP_E_TIMEOUT).  Synchronises `stream`, then copies the
- * word of `workspace` (as passed to kmpp_seed / kmpp_seed_batched) into
- * *out.  Returns KMPP_OK or KMPP_E_HIP. */
+ * KMPP_E_NONFINITE, KMPP_E_TIMEOUT, KMPP_E_WORKSPACE).  Synchronises
+ * `stream`, then copies the word of `workspace` (as passed to kmpp_seed,
+ * kmpp_seed_batched, kmpp_lloyd or kmpp_seed_parallel) into *out.  Returns
+ * KMPP_OK or KMPP_E_HIP. */
 int kmpp_status(const void* workspace, void* stream, int32_t* out);
 
 /* Graph capture helpers: capture the work a sequence of calls enqueues on
@@ -288,7 +292,7 @@ int kmpp_graph_launch(kmpp_graph g, void* stream);
 int kmpp_graph_destroy(kmpp_graph g);
 
 /* Tuning table: text lines
- * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <nontemporal>]"
+ * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <row path>]"
  * override the built-in choices for the seed pass; lines
  * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
  * alpha) set the batched planner's cost model.  Returns the number of
