@@ -95,6 +95,22 @@ enum {
 enum { KMPP_ROWS_CACHED = 0, KMPP_ROWS_NONTEMPORAL = 1, KMPP_ROWS_BUFFER = 2 };
 enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
 
+/*
+ * Where each draw runs (kmpp_seed_opts.draw).  Both follow the same steps
+ * in the same order, so for one launch shape they pick the same seeds.
+ *   KMPP_DRAW_AUTO    the tuning table's choice for (format, d), else PASS
+ *   KMPP_DRAW_PASS    every workgroup of pass m+1 draws seed m at its start
+ *                     from pass m's D and tile sums (one launch per seed;
+ *                     passes then write D and tile sums to alternating
+ *                     buffers, every row's D each pass).  Used where it
+ *                     applies (unweighted seeding, exact widths, at most 2048
+ *                     tiles, the tile sums or one tile's D within the LDS
+ *                     share that keeps the pass's occupancy), else KERNEL.
+ *   KMPP_DRAW_KERNEL  a one-workgroup draw kernel after each pass (two
+ *                     launches per seed; D updated in place where it changed)
+ */
+enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2 };
+
 /* Optional knobs of kmpp_seed (pass NULL for defaults). */
 typedef struct kmpp_seed_opts {
   uint32_t instance;    /* Philox instance id: counter word 1 (default 0) */
@@ -109,10 +125,11 @@ typedef struct kmpp_seed_opts {
                            committed, [2m+1] = its FP32 nearest distance recomputed from the
                            original FP32 row against the previous seeds. */
   void* step_events;    /* host array of 2K hipEvent_t or NULL: [2m-2] and [2m-1] track the
-                           start and the stop of pass m's kernel (profiling only) */
+                           start and the stop of pass m's kernel, its drawer included
+                           (profiling only) */
   int32_t centre_source;/* where the passes take the current centre from: 0 (default: LDS),
                            KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR or KMPP_CENTRE_GLOBAL */
-  int32_t reserved;     /* 0 */
+  int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS or KMPP_DRAW_KERNEL */
 } kmpp_seed_opts;
 
 /*

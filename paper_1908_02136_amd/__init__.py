@@ -25,6 +25,7 @@ KMPP_ROWS_CACHED, KMPP_ROWS_NONTEMPORAL, KMPP_ROWS_BUFFER = 0, 1, 2
 KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR, KMPP_CENTRE_GLOBAL = 1, 2, 3
 ROW_PATHS = {"cached": KMPP_ROWS_CACHED, "nontemporal": KMPP_ROWS_NONTEMPORAL, "buffer": KMPP_ROWS_BUFFER}
 CENTRE_SOURCES = {"lds": KMPP_CENTRE_LDS, "scalar": KMPP_CENTRE_SCALAR, "global": KMPP_CENTRE_GLOBAL}
+KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL = 0, 1, 2
 OK, W_DEGENERATE = 0, 1
 E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT = -1, -2, -3, -4, -5, -6
 MAX_D = 4096
@@ -50,7 +51,7 @@ class SeedOpts(ctypes.Structure):
     _fields_ = [("instance", ctypes.c_uint32), ("threads", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
                 ("loads_per_lane", ctypes.c_int16), ("row_loads", ctypes.c_int16),
                 ("out_recheck", ctypes.c_void_p), ("step_events", ctypes.c_void_p),
-                ("centre_source", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("centre_source", ctypes.c_int32), ("draw", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -161,11 +162,13 @@ def kmpp_seed_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> 
 def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D=None, out_idx=None, Xq=None,
               Xq_exp=None, dtype: int = KMPP_F32, instance: int = 0, threads: int = 0, rows_per_tile: int = 0,
               loads_per_lane: int = 0, row_loads: int = -1, centre_source: int = 0, out_recheck=None,
-              step_events=None, ws=None, stream=None):
+              step_events=None, draw: int = KMPP_DRAW_AUTO, ws=None, stream=None):
     """k-means++ seeding of the rows of X (FP32 [N, d]).  Returns
     (idx int64 [K], centers FP32 [K, d], D FP32 [N], workspace).
     ``row_loads`` (KMPP_ROWS_*) and ``centre_source`` (KMPP_CENTRE_*) pick
-    the memory spaces of the passes (-1 / 0: tuned default)."""
+    the memory spaces of the passes (-1 / 0: tuned default); ``draw``
+    (KMPP_DRAW_*) runs each draw in an extra workgroup of the pass launch or
+    in a kernel of its own."""
     _require_cuda(X, Xq, Xq_exp)
     N, d = X.shape
     dev = X.device
@@ -175,7 +178,7 @@ def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D
     if ws is None:
         ws = workspace(kmpp_seed_workspace_bytes(N, d, K, dtype), dev)
     opts = SeedOpts(instance, threads, rows_per_tile, loads_per_lane, row_loads,
-                    None if out_recheck is None else out_recheck.data_ptr(), step_events, centre_source, 0)
+                    None if out_recheck is None else out_recheck.data_ptr(), step_events, centre_source, draw)
     rc = lib().kmpp_seed(_ptr(X), N, d, K, seed, _ptr(out_centers), _ptr(out_D), _ptr(out_idx), _ptr(Xq),
                          _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "kmpp_seed")

@@ -25,6 +25,7 @@ bool valid_dtype(int dtype) { return dtype == KMPP_F32 || dtype == KMPP_BF16 || 
 // ---- tuning table: (dtype, d) -> launch schedule
 struct SeedTune {
   int threads, rpt, u, ntl;  // u, ntl (row path): 0 / -1 = automatic
+  int draw;                  // KMPP_DRAW_PASS, KMPP_DRAW_KERNEL or 0 (automatic)
 };
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, SeedTune> g_tune;
@@ -37,20 +38,28 @@ bool tuned(int dtype, int d, SeedTune* t) {
   return true;
 }
 
+// Most tiles for the draw at pass start (every workgroup reads every tile sum).
+constexpr int kDrawAtStartTiles = 2048;
+
 // Rows larger than the 256 MiB last-level cache are streamed with
 // non-temporal loads; smaller ones stay cached between passes.
 constexpr int64_t kCachedRowBytes = 256ll << 20;
 
 struct SeedLayout {
-  size_t tsum, D, idx, total;
+  size_t tsum, tsum2, D, D2, idx, total;  // tsum2, D2: the second buffers of the draw at pass start
 };
 
 SeedLayout seed_layout(int64_t N, int K) {
   SeedLayout L;
   size_t off = sizeof(Ctl);
+  const size_t tiles = align256(sizeof(double) * (size_t)std::min<int64_t>(N, kMaxTiles));
   L.tsum = off;
-  off += align256(sizeof(double) * (size_t)std::min<int64_t>(N, kMaxTiles));
+  off += tiles;
+  L.tsum2 = off;
+  off += tiles;
   L.D = off;
+  off += align256(sizeof(float) * (size_t)N);
+  L.D2 = off;
   off += align256(sizeof(float) * (size_t)N);
   L.idx = off;
   off += align256(sizeof(int64_t) * (size_t)K);
@@ -77,8 +86,8 @@ const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, int rl, in
 }  // namespace
 
 int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, const SeedVariant** var,
-                     int* rpt_out, int* ntiles_out) {
-  int nt = 256, rpt = 0, u = 8;
+                     int* rpt_out, int* ntiles_out, int* draw_out) {
+  int nt = 256, rpt = 0, u = 8, draw = KMPP_DRAW_PASS;
   int ntl = (int64_t)N * d * elem_bytes(dtype) > kCachedRowBytes ? 1 : 0;
   SeedTune t;
   if (tuned(dtype, d, &t)) {
@@ -86,7 +95,9 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
     rpt = t.rpt;
     if (t.u > 0) u = t.u;
     if (t.ntl >= 0) ntl = t.ntl;
+    if (t.draw) draw = t.draw;
   }
+  if (opts && opts->draw) draw = opts->draw;
   if (opts && opts->threads) nt = opts->threads;
   if (opts && opts->rows_per_tile > 0) rpt = opts->rows_per_tile;
   if (opts && opts->loads_per_lane > 0) u = opts->loads_per_lane;
@@ -112,6 +123,7 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   *var = v;
   *rpt_out = (int)r;
   *ntiles_out = (int)((N + r - 1) / r);
+  *draw_out = draw;
   return KMPP_OK;
 }
 
@@ -124,8 +136,8 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   const SeedLayout L = seed_layout(N, K);
   if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
   const SeedVariant* v = nullptr;
-  int rpt = 0, ntiles = 0;
-  const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles);
+  int rpt = 0, ntiles = 0, draw = 0;
+  const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles, &draw);
   if (rc != KMPP_OK) return rc;
   char* ws = static_cast<char*>(workspace);
 
@@ -137,6 +149,8 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   p.idx = out_idx ? out_idx : reinterpret_cast<int64_t*>(ws + L.idx);
   p.D = out_D ? out_D : reinterpret_cast<float*>(ws + L.D);
   p.tsum = reinterpret_cast<double*>(ws + L.tsum);
+  p.tsum_w = p.tsum;
+  p.Dw = p.D;
   p.ctl = reinterpret_cast<Ctl*>(ws);
   p.recheck = opts ? opts->out_recheck : nullptr;
   p.N = N;
@@ -149,6 +163,18 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   p.seed = seed;
   p.wts = wts;
   p.tag = tag;
+  // the draw at pass start (unweighted seeding, exact-width passes): every
+  // workgroup reads all tile sums, so their number is bounded, and its LDS
+  // staging must leave the pass's occupancy alone (160 KiB of LDS per CU,
+  // 2048 threads)
+  const size_t draw_lds = std::max(sizeof(double) * (size_t)ntiles, sizeof(float) * (size_t)rpt);
+  const bool at_start = draw == KMPP_DRAW_PASS && v->fn_drawer && !wts && ntiles <= kDrawAtStartTiles &&
+                        draw_lds <= (size_t)160 * 1024 * v->nt / 2048;
+  const void* pass_fn = at_start ? v->fn_drawer : v->fn;
+  // its buffers: pass m writes D to Dbuf[(K - m) % 2], so pass K ends in the
+  // caller's D, and its tile sums to Tbuf[m % 2]
+  float* const Dbuf[2] = {p.D, reinterpret_cast<float*>(ws + L.D2)};
+  double* const Tbuf[2] = {p.tsum, reinterpret_cast<double*>(ws + L.tsum2)};
   hipEvent_t* ev = opts ? static_cast<hipEvent_t*>(opts->step_events) : nullptr;
 
   void* args[] = {&p};
@@ -159,18 +185,26 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
         hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) != hipSuccess)
       return KMPP_E_HIP;
   }
-  const size_t shmem = sizeof(float) * (size_t)d;
+  const size_t shmem = std::max(sizeof(float) * (size_t)d, at_start ? draw_lds : (size_t)0);
+  const dim3 grid((unsigned)ntiles);
   for (int m = 1; m <= K; ++m) {
     p.pass = m;
+    if (at_start) {
+      p.Dw = Dbuf[(K - m) % 2];
+      p.D = Dbuf[(K - m + 1) % 2];  // pass m-1's (not read by pass 1)
+      p.tsum_w = Tbuf[m % 2];
+      p.tsum = Tbuf[(m + 1) % 2];
+    }
     // with step events, the events are attached to the dispatch itself and
     // track the kernel's own start and stop
     const hipError_t le =
-        ev ? hipExtLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream,
-                                ev[2 * (m - 1)], ev[2 * (m - 1) + 1], 0)
-           : hipLaunchKernel(v->fn, dim3((unsigned)ntiles), dim3((unsigned)v->nt), args, shmem, stream);
+        ev ? hipExtLaunchKernel(pass_fn, grid, dim3((unsigned)v->nt), args, shmem, stream, ev[2 * (m - 1)],
+                                ev[2 * (m - 1) + 1], 0)
+           : hipLaunchKernel(pass_fn, grid, dim3((unsigned)v->nt), args, shmem, stream);
     if (le != hipSuccess) return KMPP_E_HIP;
-    if (m < K && hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
-                     hipSuccess)
+    if (m < K && !at_start &&
+        hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
+            hipSuccess)
       return KMPP_E_HIP;
   }
   return KMPP_OK;
@@ -198,6 +232,7 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
     if (!Xq || !aligned(Xq, 16)) return KMPP_E_INVALID;
     if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
   }
+  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_KERNEL)) return KMPP_E_INVALID;
   return seed_run(X, N, d, K, seed, opts ? opts->instance : 0u, 0u, nullptr, out_centers, out_D, out_idx, Xq, Xq_exp,
                   dtype, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream_));
 }
@@ -353,12 +388,12 @@ int kmpp_tune_load(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   while (fgets(line, sizeof(line), f)) {
     char kind[32], key[32];
-    int dt, d, nt, rpt, u = 0, ntl = -1;
+    int dt, d, nt, rpt, u = 0, ntl = -1, draw = 0;
     double val;
-    const int got = sscanf(line, "%31s %d %d %d %d %d %d", kind, &dt, &d, &nt, &rpt, &u, &ntl);
+    const int got = sscanf(line, "%31s %d %d %d %d %d %d %d", kind, &dt, &d, &nt, &rpt, &u, &ntl, &draw);
     if (got >= 5 && strcmp(kind, "seed") == 0 && valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0 &&
-        (u == 0 || u == 8 || u == 16) && ntl >= -1 && ntl <= 1) {
-      g_tune[{dt, d}] = SeedTune{nt, rpt, u, ntl};
+        (u == 0 || u == 8 || u == 16) && ntl >= -1 && ntl <= 1 && draw >= 0 && draw <= KMPP_DRAW_KERNEL) {
+      g_tune[{dt, d}] = SeedTune{nt, rpt, u, ntl, draw};
       ++n;
     } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "batched") == 0 &&
                batched_tune_set(key, val) == KMPP_OK) {

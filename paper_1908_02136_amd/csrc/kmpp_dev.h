@@ -24,7 +24,7 @@ struct ElemBytes<FMT_FP8> { static constexpr int value = 1; };
 // First 256 bytes of every workspace.
 struct Ctl {
   int32_t status;      // KMPP_OK, a warning (>0) or an error (<0)
-  uint32_t arrive;     // seed loop: workgroups arrived, counted over all passes of a run
+  uint32_t arrive;     // reserved (0)
   uint32_t nflag;      // assignment: rows queued for the direct-form recheck
   uint32_t pad[61];
 };

@@ -34,6 +34,8 @@ struct SeedParams {
   uint64_t seed;
   const int32_t* wts;    // weighted seeding: row weights (draws proportional to w * D), or null
   uint32_t tag;          // Philox counter word 3 of the draws (0: the k-means++ stream)
+  float* Dw;             // draw at pass start: this pass's D (every row; D holds the previous pass's)
+  double* tsum_w;        // draw at pass start: this pass's tile sums (tsum holds the previous pass's)
 };
 
 // One compiled seed-pass kernel.
@@ -47,6 +49,7 @@ struct SeedVariant {
   int nt;
   int rows_per_iter; // rows one workgroup covers per loop iteration
   const void* fn;
+  const void* fn_drawer;  // the same pass drawing the previous seed at its start, or null
 };
 
 const std::vector<SeedVariant>& seed_variants();

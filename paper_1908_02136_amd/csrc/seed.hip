@@ -1,13 +1,17 @@
 // seed.hip -- the k-means++ seed loop (paper, Section II, Algorithms 1-2).
 //
-// Two launches per seed.  The pass kernel m (1..K) streams the point rows
+// One launch per seed.  The pass kernel m (1..K) streams the point rows
 // once, updates every point's nearest squared distance
 // D = min(D, ||x - c_{m-1}||^2) and reduces D per workgroup tile into an FP64
-// tile sum.  For m < K a one-workgroup draw kernel then takes seed m by
-// inverting the FP64 cumulative distribution of D (tile sums, then the
-// owning tile's rows) at t = u_m * sum(D).  The next pass reads that
-// original FP32 row, broadcasts it from LDS and stores it in out_centers[m].
-// Nothing returns to the host between seeds.
+// tile sum.  For m < K seed m is then taken by inverting the FP64
+// cumulative distribution of D (tile sums, then the owning tile's rows) at
+// t = u_m * sum(D), either by every workgroup of pass m+1 at its start (one
+// launch per seed; pass m+1 then writes D and its tile sums to the other of
+// two buffers, so pass m's stay intact while any workgroup still draws) or
+// by a one-workgroup draw kernel between the passes (two launches per seed;
+// weighted seeding, very many tiles, or where the tuning table says so).
+// Pass m+1 reads that original FP32 row, broadcasts it from LDS and stores
+// it in out_centers[m].  Nothing returns to the host between seeds.
 //
 // Row streaming: a row of d elements is split into 16-byte chunks; a group
 // of G lanes covers one row (G*CPL chunks), so one wave-wide load reads 64/G
@@ -77,10 +81,11 @@ constexpr int kDrawNT = 256;
 constexpr int kDrawPer = 32;   // tile sums per thread: kMaxTiles <= kDrawNT * kDrawPer
 constexpr int kDrawRows = 16;  // D values per thread kept in registers
 
-// Exclusive scan of one double per thread over kDrawNT threads with a
-// single barrier; fixed association order.  Returns (exclusive, total).
+// Exclusive scan of one double per thread over NT threads with a single
+// barrier; fixed association order.  Returns (exclusive, total).
+template <int NT>
 __device__ __forceinline__ double2 draw_scan(double v, double* sh) {
-  constexpr int NW = kDrawNT / 64;
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double x = v;
 #pragma unroll
@@ -103,8 +108,9 @@ __device__ __forceinline__ double2 draw_scan(double v, double* sh) {
 }
 
 // (min a, max b) over the workgroup with one barrier.
+template <int NT>
 __device__ __forceinline__ int2 draw_minmax(int a, int b, int2* sh) {
-  constexpr int NW = kDrawNT / 64;
+  constexpr int NW = NT / 64;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     a = min(a, __shfl_xor(a, o, 64));
@@ -144,7 +150,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
     part += v[k];
     if (v[k] > 0.0) lastpos = b0 + k;
   }
-  const double2 sc = draw_scan(part, sh);
+  const double2 sc = draw_scan<NT>(part, sh);
   const double T = sc.y;
   const double u = draw_uniform(p.seed, (uint32_t)p.pass, p.inst, p.tag);
 
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
       }
       run = nr;
     }
-    const int2 tm = draw_minmax(cand, lastpos, shm);
+    const int2 tm = draw_minmax<NT>(cand, lastpos, shm);
     if (cand != NONE && cand == tm.x) s_lo = lo;
     const bool inside = tm.x != NONE;  // else rounding put t at or past the total
     int tile = inside ? tm.x : tm.y;
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
         part2 += (double)dv[k];
         if (dv[k] > Share(0)) lastrow = (int)(q0 - r0) + k;
       }
-      const double2 sc2 = draw_scan(part2, sh);
+      const double2 sc2 = draw_scan<NT>(part2, sh);
       if (inside) {
         double r = tlo + sc2.x;
 #pragma unroll
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
         part2 += dk;
         if (dk > 0.0) lastrow = (int)(q0 - r0) + k;
       }
-      const double2 sc2 = draw_scan(part2, sh);
+      const double2 sc2 = draw_scan<NT>(part2, sh);
       if (inside) {
         double r = tlo + sc2.x;
         for (int k = 0; k < nq && found == NONE; ++k) {
@@ -225,7 +231,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
         }
       }
     }
-    const int2 fm = draw_minmax(found, lastrow, shm);
+    const int2 fm = draw_minmax<NT>(found, lastrow, shm);
     seed_row = r0 + (fm.x != NONE ? fm.x : (fm.y >= 0 ? fm.y : n - 1));
   }
 
@@ -252,14 +258,135 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
   if (tid == 0) p.idx[p.pass] = seed_row;
 }
 
+// The draw of seed step = pass - 1 at the start of every workgroup of the
+// pass (the kernel boundary makes the previous pass's D and tile sums
+// visible; this pass writes to the other buffers).  The same fixed-order
+// steps as draw_seed on the same values, so every workgroup finds the same
+// row, and for one NT the draw kernel finds it too; the tile sums and then
+// the owner tile's D are staged in LDS (lds: max(8 ntiles, 4 rows_per_tile)
+// bytes).  Workgroup 0 records the index (and the precision recheck) and
+// raises the status.  Returns the row; lds is free again on return.
+template <int NT>
+__device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
+  constexpr int NW = NT / 64;
+  __shared__ double sh[NW];
+  __shared__ int2 shm[NW];
+  __shared__ float shf[NW];
+  __shared__ double s_lo;
+  double* ts = reinterpret_cast<double*>(lds);
+  const int tid = threadIdx.x;
+  const int G = p.ntiles;
+  const int NONE = INT_MAX;
+  const int step = p.pass - 1;
+  const bool lead = blockIdx.x == 0;
+
+  for (int i = tid; i < G; i += NT) ts[i] = p.tsum[i];
+  __syncthreads();
+  // the tiles: contiguous blocks per thread, fixed-order FP64 scan
+  const int per = (G + NT - 1) / NT;
+  const int b0 = min(G, tid * per);
+  const int nb = max(0, min(per, G - b0));
+  double part = 0.0;
+  int lastpos = -1;
+  for (int k = 0; k < nb; ++k) {
+    const double v = ts[b0 + k];
+    part += v;
+    if (v > 0.0) lastpos = b0 + k;
+  }
+  const double2 sc = draw_scan<NT>(part, sh);
+  const double T = sc.y;
+  const double u = draw_uniform(p.seed, (uint32_t)step, p.inst, p.tag);
+
+  int64_t seed_row;
+  if (!isfinite(T)) {
+    if (lead && tid == 0) raise_status(p.ctl, KMPP_E_NONFINITE);
+    seed_row = 0;
+  } else if (T == 0.0) {
+    if (lead && tid == 0) raise_status(p.ctl, KMPP_W_DEGENERATE);
+    seed_row = uniform_index(u, p.N);
+  } else {
+    const double t = __dmul_rn(u, T);
+    int cand = NONE;
+    double run = sc.x, lo = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      const double nr = run + ts[b0 + k];
+      if (cand == NONE && nr > t) {
+        cand = b0 + k;
+        lo = run;
+      }
+      run = nr;
+    }
+    const int2 tm = draw_minmax<NT>(cand, lastpos, shm);  // ends with a barrier: ts is free
+    if (cand != NONE && cand == tm.x) s_lo = lo;
+    const bool inside = tm.x != NONE;
+    int tile = inside ? tm.x : tm.y;
+    if (tile < 0 || tile >= G) tile = G - 1;
+    // the owner tile's D, staged in LDS, same blocks as draw_seed
+    const int64_t r0 = (int64_t)tile * p.rows_per_tile;
+    const int64_t r1 = min(p.N, r0 + (int64_t)p.rows_per_tile);
+    const int n = (int)(r1 - r0);
+    for (int i = tid; i < n; i += NT) lds[i] = p.D[r0 + i];
+    __syncthreads();
+    const double tlo = inside ? s_lo : 0.0;
+    const int per2 = (n + NT - 1) / NT;
+    const int j0 = min(n, tid * per2);
+    const int nq = max(0, min(per2, n - j0));
+    int found = NONE, lastrow = -1;
+    double part2 = 0.0;
+    for (int k = 0; k < nq; ++k) {
+      const float dk = lds[j0 + k];
+      part2 += (double)dk;
+      if (dk > 0.0f) lastrow = j0 + k;
+    }
+    const double2 sc2 = draw_scan<NT>(part2, sh);
+    if (inside) {
+      double r = tlo + sc2.x;
+      for (int k = 0; k < nq && found == NONE; ++k) {
+        r += (double)lds[j0 + k];
+        if (r > t) found = j0 + k;
+      }
+    }
+    const int2 fm = draw_minmax<NT>(found, lastrow, shm);  // ends with a barrier: lds is free
+    seed_row = r0 + (fm.x != NONE ? fm.x : (fm.y >= 0 ? fm.y : n - 1));
+  }
+
+  if (lead) {
+    // precision forms: as in draw_seed
+    if (p.recheck != nullptr) {
+      const float* xr = p.X + seed_row * (int64_t)p.d;
+      float best = INFINITY;
+      for (int j = tid; j < step; j += NT) {
+        const float* c = p.centers + (int64_t)j * p.d;  // written by earlier passes
+        float a = 0.0f;
+        for (int k = 0; k < p.d; ++k) {
+          const float df = xr[k] - c[k];
+          a = fmaf(df, df, a);
+        }
+        best = fminf(best, a);
+      }
+      best = block_minf<NT>(best, shf);
+      if (tid == 0) {
+        p.recheck[2 * (int64_t)step] = p.D[seed_row];
+        p.recheck[2 * (int64_t)step + 1] = best;
+      }
+    }
+    if (tid == 0) p.idx[step] = seed_row;
+  }
+  __syncthreads();
+  return seed_row;
+}
+
 // ---------------------------------------------------------------- S2
 // One pass: the row path RL and the centre source CS are template
 // parameters (the memory spaces Section II compares).
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS>
+// DRAWER: every workgroup first draws seed m-1 (m >= 2) from pass m-1's D
+// and tile sums; this pass writes every row's D to Dw and its tile sums to
+// tsum_w (the other buffers).  Else D is updated in place where it changed.
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS, bool DRAWER>
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, RL>;
   constexpr int NW = NT / 64;
-  extern __shared__ float cs[];  // centre row, d floats (CEN_LDS)
+  extern __shared__ __align__(16) float cs[];  // centre row, d floats (CEN_LDS); the drawer's staging
   __shared__ double red[NW];
 
   const int tid = threadIdx.x;
@@ -268,8 +395,14 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   const int64_t t0 = (int64_t)blockIdx.x * p.rows_per_tile;
   const int64_t t1 = min(p.N, t0 + (int64_t)p.rows_per_tile);
 
-  // centre c_{pass-1}: the original FP32 row of the previous seed
-  const int64_t cidx = p.idx[p.pass - 1];
+  // centre c_{pass-1}: the original FP32 row of the previous seed (drawn
+  // here first with DRAWER; loading this wave's first rows before the draw
+  // costs more occupancy than it hides latency)
+  int64_t cidx;
+  if constexpr (DRAWER)
+    cidx = p.pass >= 2 ? draw_at_start<NT>(p, cs) : p.idx[0];
+  else
+    cidx = p.idx[p.pass - 1];
   const float* cg = p.X + cidx * (int64_t)d;
   const int64_t prev = (FMT != FMT_F32) ? cidx : -1;
   S st;
@@ -295,11 +428,15 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
 
   double acc = 0.0;
   float* D = p.D;
+  auto sink = [&](int64_t row, float dn, bool changed) {
+    if constexpr (DRAWER)
+      p.Dw[row] = dn;
+    else if (changed)
+      D[row] = dn;
+    acc += p.wts ? (double)dn * (double)p.wts[row] : (double)dn;
+  };
   for (int64_t base = t0 + (int64_t)st.wave * S::R; base < t1; base += (int64_t)NW * S::R)
-    st.iter(p, base, t1, first, prev, [&](int64_t row, float dn, bool changed) {
-      if (changed) D[row] = dn;
-      acc += p.wts ? (double)dn * (double)p.wts[row] : (double)dn;
-    });
+    st.iter(p, base, t1, first, prev, sink);
 
   acc = wave_sum(acc);
   if ((tid & 63) == 0) red[st.wave] = acc;
@@ -308,12 +445,12 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) s += red[w];
-    p.tsum[blockIdx.x] = s;
+    (DRAWER ? p.tsum_w : p.tsum)[blockIdx.x] = s;
   }
 }
 
 // ---------------------------------------------------------------- registry
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS = CEN_LDS>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS = CEN_LDS, bool WITH_DRAWER = false>
 static SeedVariant make_variant(int dexact) {
   SeedVariant v;
   v.fmt = FMT;
@@ -327,28 +464,33 @@ static SeedVariant make_variant(int dexact) {
   v.rl = RL;
   v.cs = CS;
   v.rows_per_iter = (NT / 64) * U * (64 / G);
-  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS>);
+  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, false>);
+  if constexpr (WITH_DRAWER)
+    v.fn_drawer = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, true>);
+  else
+    v.fn_drawer = nullptr;
   return v;
 }
 
 // Rows in 16-byte (d = 2: 8-byte) chunks for exact widths, U = 8 loads per
-// lane; the widths of the named workloads also with U = 16.
+// lane; the widths of the named workloads also with U = 16; each also with
+// the drawer.
 #define KMPP_EXACT(NT, L)                                                                                   \
-  make_variant<FMT_F32, 8, 1, 1, 8, true, NT, L>(2), make_variant<FMT_F32, 16, 1, 1, 8, true, NT, L>(4),      \
-      make_variant<FMT_F32, 16, 2, 1, 8, true, NT, L>(8), make_variant<FMT_F32, 16, 4, 1, 8, true, NT, L>(16), \
-      make_variant<FMT_F32, 16, 8, 1, 8, true, NT, L>(32), make_variant<FMT_F32, 16, 16, 1, 8, true, NT, L>(64), \
-      make_variant<FMT_F32, 16, 32, 1, 8, true, NT, L>(128), make_variant<FMT_F32, 16, 64, 1, 8, true, NT, L>(256), \
-      make_variant<FMT_F32, 16, 64, 2, 4, true, NT, L>(512),                                                \
-      make_variant<FMT_F32, 16, 8, 1, 16, true, NT, L>(32), make_variant<FMT_F32, 16, 16, 1, 16, true, NT, L>(64), \
-      make_variant<FMT_F32, 16, 32, 1, 16, true, NT, L>(128),                                               \
-      make_variant<FMT_BF16, 16, 1, 1, 8, true, NT, L>(8), make_variant<FMT_BF16, 16, 2, 1, 8, true, NT, L>(16), \
-      make_variant<FMT_BF16, 16, 4, 1, 8, true, NT, L>(32), make_variant<FMT_BF16, 16, 8, 1, 8, true, NT, L>(64), \
-      make_variant<FMT_BF16, 16, 16, 1, 8, true, NT, L>(128), make_variant<FMT_BF16, 16, 32, 1, 8, true, NT, L>(256), \
-      make_variant<FMT_BF16, 16, 8, 1, 16, true, NT, L>(64), make_variant<FMT_BF16, 16, 16, 1, 16, true, NT, L>(128), \
-      make_variant<FMT_FP8, 16, 1, 1, 8, true, NT, L>(16), make_variant<FMT_FP8, 16, 2, 1, 8, true, NT, L>(32), \
-      make_variant<FMT_FP8, 16, 4, 1, 8, true, NT, L>(64), make_variant<FMT_FP8, 16, 8, 1, 8, true, NT, L>(128), \
-      make_variant<FMT_FP8, 16, 16, 1, 8, true, NT, L>(256),                                                \
-      make_variant<FMT_FP8, 16, 4, 1, 16, true, NT, L>(64), make_variant<FMT_FP8, 16, 8, 1, 16, true, NT, L>(128)
+  make_variant<FMT_F32, 8, 1, 1, 8, true, NT, L, CEN_LDS, true>(2), make_variant<FMT_F32, 16, 1, 1, 8, true, NT, L, CEN_LDS, true>(4),      \
+      make_variant<FMT_F32, 16, 2, 1, 8, true, NT, L, CEN_LDS, true>(8), make_variant<FMT_F32, 16, 4, 1, 8, true, NT, L, CEN_LDS, true>(16), \
+      make_variant<FMT_F32, 16, 8, 1, 8, true, NT, L, CEN_LDS, true>(32), make_variant<FMT_F32, 16, 16, 1, 8, true, NT, L, CEN_LDS, true>(64), \
+      make_variant<FMT_F32, 16, 32, 1, 8, true, NT, L, CEN_LDS, true>(128), make_variant<FMT_F32, 16, 64, 1, 8, true, NT, L, CEN_LDS, true>(256), \
+      make_variant<FMT_F32, 16, 64, 2, 4, true, NT, L, CEN_LDS, true>(512),                                                \
+      make_variant<FMT_F32, 16, 8, 1, 16, true, NT, L, CEN_LDS, true>(32), make_variant<FMT_F32, 16, 16, 1, 16, true, NT, L, CEN_LDS, true>(64), \
+      make_variant<FMT_F32, 16, 32, 1, 16, true, NT, L, CEN_LDS, true>(128),                                               \
+      make_variant<FMT_BF16, 16, 1, 1, 8, true, NT, L, CEN_LDS, true>(8), make_variant<FMT_BF16, 16, 2, 1, 8, true, NT, L, CEN_LDS, true>(16), \
+      make_variant<FMT_BF16, 16, 4, 1, 8, true, NT, L, CEN_LDS, true>(32), make_variant<FMT_BF16, 16, 8, 1, 8, true, NT, L, CEN_LDS, true>(64), \
+      make_variant<FMT_BF16, 16, 16, 1, 8, true, NT, L, CEN_LDS, true>(128), make_variant<FMT_BF16, 16, 32, 1, 8, true, NT, L, CEN_LDS, true>(256), \
+      make_variant<FMT_BF16, 16, 8, 1, 16, true, NT, L, CEN_LDS, true>(64), make_variant<FMT_BF16, 16, 16, 1, 16, true, NT, L, CEN_LDS, true>(128), \
+      make_variant<FMT_FP8, 16, 1, 1, 8, true, NT, L, CEN_LDS, true>(16), make_variant<FMT_FP8, 16, 2, 1, 8, true, NT, L, CEN_LDS, true>(32), \
+      make_variant<FMT_FP8, 16, 4, 1, 8, true, NT, L, CEN_LDS, true>(64), make_variant<FMT_FP8, 16, 8, 1, 8, true, NT, L, CEN_LDS, true>(128), \
+      make_variant<FMT_FP8, 16, 16, 1, 8, true, NT, L, CEN_LDS, true>(256),                                                \
+      make_variant<FMT_FP8, 16, 4, 1, 16, true, NT, L, CEN_LDS, true>(64), make_variant<FMT_FP8, 16, 8, 1, 16, true, NT, L, CEN_LDS, true>(128)
 
 // Any d: one element per chunk, G = min(64, pow2 >= d) lanes per row.
 #define KMPP_GENERIC(NT)                                                                                    \

@@ -2,17 +2,21 @@
 
 * Seed pass: for each (storage format, d) it times whole seeding runs over a
   grid of (threads per workgroup, rows per tile, row loads in flight per
-  lane, cached or non-temporal row loads) and keeps the fastest;
+  lane, cached or non-temporal row loads, draw at the start of the next pass
+  or in a draw kernel) and keeps the fastest;
 * batched planner: it times the 512-instance batch over a grid of the
   cost-model knobs (workgroups per CU, the cap on one instance's time) and
   keeps the fastest.
 
 The result is written as text lines
-``seed <dtype> <d> <threads> <rows> <loads per lane> <non-temporal>`` and
-``batched <key> <value>`` to ``tune_table.txt`` next to the library, which
-the binding loads at import (``kmpp_tune_load``).
+``seed <dtype> <d> <threads> <rows> <loads per lane> <non-temporal> <draw>``
+(draw: 1 at the start of the next pass, 2 draw kernel) and ``batched <key> <value>`` to
+``tune_table.txt`` next to the library, which the binding loads at import
+(``kmpp_tune_load``).
 
     python -m paper_1908_02136_amd.tune [--quick] [--out PATH]
+        [--only DTYPE:D,...]   retune these cases, keep the table's other lines
+        [--draw-only]          keep every schedule, re-time only the draw
 """
 from __future__ import annotations
 
@@ -38,32 +42,67 @@ def _time(fn, reps=2):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_seed(kl, cases, quick):
+# the draw at pass start applies up to this many tiles (every workgroup reads
+# every tile sum)
+DRAW_AT_START_TILES = 2048
+
+
+def tune_draw(kl, X, K, Xq, E, dtype, nt, rpt, u, ntl):
+    """Faster draw placement (KMPP_DRAW_PASS or KMPP_DRAW_KERNEL) for one schedule."""
+    ms = {}
+    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL):
+        ms[draw] = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt, rows_per_tile=rpt,
+                                              loads_per_lane=u, row_loads=ntl, draw=draw), reps=3)
+        print(f"seed dtype={dtype} d={X.shape[1]} N={X.shape[0]} K={K} threads={nt} rows={rpt} u={u} nt={ntl} "
+              f"draw={draw}: {ms[draw]:.3f} ms", flush=True)
+    return min(ms, key=ms.get)
+
+
+def _case_rows(kl, dtype, d, N):
+    X = torch.randn((N, d), device="cuda")
+    Xq = E = None
+    if dtype:
+        Xq, E = kl.kmpp_quantize(X, dtype)
+    return X, Xq, E
+
+
+def tune_seed(kl, cases, quick, keep=None):
+    """Seed lines for `cases`; `keep` maps (dtype, d) to an existing line's
+    schedule (threads, rows, u, non-temporal) to re-time only the draw."""
     lines = []
     for dtype, d, N, K in cases:
-        X = torch.randn((N, d), device="cuda")
-        Xq = E = None
-        if dtype:
-            Xq, E = kl.kmpp_quantize(X, dtype)
+        X, Xq, E = _case_rows(kl, dtype, d, N)
+        if keep is not None and (dtype, d) in keep:
+            nt, rpt, u, ntl = keep[(dtype, d)]
+            draw = tune_draw(kl, X, K, Xq, E, dtype, nt, rpt, u, ntl)
+            lines.append(f"seed {dtype} {d} {nt} {rpt} {u} {ntl} {draw}")
+            del X, Xq, E
+            torch.cuda.empty_cache()
+            continue
         row_bytes = d * {0: 4, 1: 2, 2: 1}[dtype]
         rpt_grid = sorted({max(1, (b // row_bytes)) for b in ([32 << 10, 64 << 10, 128 << 10, 256 << 10]
                                                                 if not quick else [64 << 10, 128 << 10])})
         best = None
         for nt in (256, 512):
             for rpt in rpt_grid:
+                draws = [kl.KMPP_DRAW_KERNEL]
+                if -(-N // rpt) <= DRAW_AT_START_TILES:
+                    draws.append(kl.KMPP_DRAW_PASS)
                 for u in (8, 16):
                     for ntl in (0, 1):
-                        try:
-                            ms = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt,
-                                                            rows_per_tile=rpt, loads_per_lane=u, row_loads=ntl))
-                        except kl.KmppError:
-                            continue
-                        print(f"seed dtype={dtype} d={d} N={N} K={K} threads={nt} rows={rpt} u={u} nt={ntl}: "
-                              f"{ms:.3f} ms", flush=True)
-                        if best is None or ms < best[0]:
-                            best = (ms, nt, rpt, u, ntl)
+                        for draw in draws:
+                            try:
+                                ms = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt,
+                                                                rows_per_tile=rpt, loads_per_lane=u, row_loads=ntl,
+                                                                draw=draw))
+                            except kl.KmppError:
+                                continue
+                            print(f"seed dtype={dtype} d={d} N={N} K={K} threads={nt} rows={rpt} u={u} nt={ntl} "
+                                  f"draw={draw}: {ms:.3f} ms", flush=True)
+                            if best is None or ms < best[0]:
+                                best = (ms, nt, rpt, u, ntl, draw)
         if best:
-            lines.append(f"seed {dtype} {d} {best[1]} {best[2]} {best[3]} {best[4]}")
+            lines.append(f"seed {dtype} {d} {best[1]} {best[2]} {best[3]} {best[4]} {best[5]}")
         del X, Xq, E
         torch.cuda.empty_cache()
     return lines
@@ -96,17 +135,35 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
+    ap.add_argument("--only", default="", help="comma list of DTYPE:D cases to retune")
+    ap.add_argument("--draw-only", action="store_true")
     args = ap.parse_args()
     import paper_1908_02136_amd as kl
     kl.lib()
-    cases = [  # (dtype, d, N, K): the shapes the benchmark runs
+    cases = [  # (dtype, d, N, K): the shapes the benchmark runs (d = 2: the paper's point sets)
         (0, 32, 1_000_000, 256), (0, 128, 4_194_304, 64), (1, 128, 4_194_304, 64), (2, 128, 4_194_304, 64),
-        (0, 64, 16_777_216, 16), (1, 64, 16_777_216, 16), (2, 64, 16_777_216, 16), (0, 2, 10_000, 16),
+        (0, 64, 16_777_216, 16), (1, 64, 16_777_216, 16), (2, 64, 16_777_216, 16), (0, 2, 4_000_000, 64),
         (0, 8, 200_000, 64), (0, 16, 200_000, 64),
     ]
+    old = {}  # (dtype, d) -> schedule of the current table
+    other = []  # its batched lines
+    if (args.only or args.draw_only) and os.path.exists(args.out):
+        for ln in open(args.out):
+            f = ln.split()
+            if len(f) >= 7 and f[0] == "seed":
+                old[(int(f[1]), int(f[2]))] = tuple(int(x) for x in f[3:7])
+            elif f and f[0] == "batched":
+                other.append(ln.strip())
     lines = ["# written by paper_1908_02136_amd/tune.py on " + torch.cuda.get_device_name(0)]
-    lines += tune_seed(kl, cases, args.quick)
-    lines += tune_batched(kl, args.quick)
+    if args.only or args.draw_only:
+        only = {tuple(int(x) for x in c.split(":")) for c in args.only.split(",") if c}
+        keep = {k: v for k, v in old.items() if k not in only}
+        lines += tune_seed(kl, [c for c in cases if (c[0], c[1]) in only or (c[0], c[1]) in keep], args.quick,
+                           keep=keep)
+        lines += other
+    else:
+        lines += tune_seed(kl, cases, args.quick)
+        lines += tune_batched(kl, args.quick)
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -68,6 +68,10 @@ def test_seed_argument_checks_need_no_gpu(kl):
     assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 0, None, ws, 16, None) == -2
     # null outputs
     assert L.kmpp_seed(fake, 10, 2, 1, 0, None, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
+    # unknown draw mode
+    opts = kl.SeedOpts(0, 0, 0, 0, -1, None, None, 0, 3)
+    assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 0, ctypes.byref(opts), ws, 1 << 30,
+                       None) == -1
 
 
 def test_other_argument_checks_need_no_gpu(kl):

@@ -68,6 +68,43 @@ def test_launch_shapes(kl, threads, rpt):
     check_seed_run(Xh.numpy(), K, 1, idx, C, D)
 
 
+@pytest.mark.parametrize("threads,rpt,K", [(256, 0, 24), (256, 64, 24), (512, 0, 24), (512, 512, 300),
+                                           (256, 5000, 24)])
+def test_draw_at_pass_start_matches_draw_kernel(kl, threads, rpt, K):
+    # the draw by every workgroup at the start of the next pass against the
+    # draw kernel: the same fixed-order steps, so at 256 threads (the draw
+    # kernel's size) the same seeds and D; at 512 threads both against the
+    # oracle.  rpt=64 gives 1930 tiles; rpt=5000 is too large a tile for the
+    # LDS share (draw kernel in both modes)
+    N, d = 123_457, 32
+    Xh = kmpp_synth.gaussian(N, d, seed=11)
+    X = Xh.cuda()
+    _say("draw at pass start vs draw kernel", N, d, K, threads, rpt)
+    a = run_seed(kl, X, K, seed=4, threads=threads, rows_per_tile=rpt, draw=kl.KMPP_DRAW_PASS)
+    b = run_seed(kl, X, K, seed=4, threads=threads, rows_per_tile=rpt, draw=kl.KMPP_DRAW_KERNEL)
+    assert a[3] == 0 and b[3] == 0
+    if threads == 256:
+        assert np.array_equal(a[0], b[0])
+        assert np.array_equal(a[2], b[2])
+    for idx, C, D, _ in (a, b):
+        check_seed_run(Xh.numpy(), K, 4, idx, C, D)
+
+
+def test_draw_at_pass_start_repeated_calls_one_workspace(kl):
+    # the D and tile-sum buffers alternate by pass and the last pass writes
+    # the caller's D whatever the parity of K: back-to-back runs on one
+    # workspace, odd and even K, each match the oracle
+    N, d = 200_003, 8
+    Xh = kmpp_synth.gaussian(N, d, seed=12)
+    X = Xh.cuda()
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, 64), "cuda")
+    for K, seed in ((64, 1), (7, 2), (64, 3), (2, 4)):
+        _say("draw at pass start, repeat", K, seed)
+        idx, C, D, st = run_seed(kl, X, K, seed=seed, ws=ws)
+        assert st == 0
+        check_seed_run(Xh.numpy(), K, seed, idx, C, D)
+
+
 def test_K1_and_K_equals_N(kl):
     Xh = kmpp_synth.gaussian(300, 5, seed=6)
     idx, C, D, st = run_seed(kl, Xh.cuda(), 1, seed=9)
