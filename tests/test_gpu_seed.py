@@ -105,6 +105,30 @@ def test_draw_at_pass_start_repeated_calls_one_workspace(kl):
         check_seed_run(Xh.numpy(), K, seed, idx, C, D)
 
 
+def test_draw_at_pass_start_edge_cases(kl):
+    # d=8 has a pass with the draw at its start: a zero sum of D (uniform
+    # draws, warning), a NaN row (error), K=1 (no draw), K=2, K=N
+    P = kl.KMPP_DRAW_PASS
+    Xh = torch.ones((1000, 8))
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 5, seed=2, draw=P)
+    assert st == kl.W_DEGENERATE
+    r = oracle.seed(Xh.numpy(), 5, seed=2)
+    assert idx.tolist() == r.idx.tolist()
+    Xn = kmpp_synth.gaussian(1000, 8, seed=3)
+    Xn[17, 2] = float("nan")
+    assert run_seed(kl, Xn.cuda(), 5, seed=2, draw=P)[3] == kl.E_NONFINITE
+    Xg = kmpp_synth.gaussian(5000, 8, seed=13)
+    for K in (1, 2):
+        idx, C, D, st = run_seed(kl, Xg.cuda(), K, seed=K, draw=P)
+        assert st == 0
+        check_seed_run(Xg.numpy(), K, K, idx, C, D)
+    Xs = kmpp_synth.gaussian(300, 8, seed=14)
+    idx, C, D, st = run_seed(kl, Xs.cuda(), 300, seed=9, draw=P)
+    assert st == 0
+    assert sorted(idx.tolist()) == list(range(300))
+    assert np.all(D == 0.0)
+
+
 def test_K1_and_K_equals_N(kl):
     Xh = kmpp_synth.gaussian(300, 5, seed=6)
     idx, C, D, st = run_seed(kl, Xh.cuda(), 1, seed=9)
