@@ -266,6 +266,26 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
 // the owner tile's D are staged in LDS (lds: max(8 ntiles, 4 rows_per_tile)
 // bytes).  Workgroup 0 records the index (and the precision recheck) and
 // raises the status.  Returns the row; lds is free again on return.
+// Copy n values to LDS with up to 8 loads per thread in flight before the
+// first store (one memory round trip per 8 * NT values).
+template <int NT, typename T, typename L>
+__device__ __forceinline__ void stage_to_lds(const T* __restrict__ src, L* dst, int n) {
+  constexpr int kB = 8;
+  for (int b = 0; b < n; b += kB * NT) {
+    T v[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + k * NT + (int)threadIdx.x;
+      v[k] = i < n ? src[i] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int i = b + k * NT + (int)threadIdx.x;
+      if (i < n) dst[i] = v[k];
+    }
+  }
+}
+
 template <int NT>
 __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
   constexpr int NW = NT / 64;
@@ -280,7 +300,7 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
   const int step = p.pass - 1;
   const bool lead = blockIdx.x == 0;
 
-  for (int i = tid; i < G; i += NT) ts[i] = p.tsum[i];
+  stage_to_lds<NT>(p.tsum, ts, G);
   __syncthreads();
   // the tiles: contiguous blocks per thread, fixed-order FP64 scan
   const int per = (G + NT - 1) / NT;
@@ -325,7 +345,7 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
     const int64_t r0 = (int64_t)tile * p.rows_per_tile;
     const int64_t r1 = min(p.N, r0 + (int64_t)p.rows_per_tile);
     const int n = (int)(r1 - r0);
-    for (int i = tid; i < n; i += NT) lds[i] = p.D[r0 + i];
+    stage_to_lds<NT>(p.D + r0, lds, n);
     __syncthreads();
     const double tlo = inside ? s_lo : 0.0;
     const int per2 = (n + NT - 1) / NT;
