@@ -11,7 +11,12 @@ seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
   roofline      the seed-pass kernel: algorithmic row bytes per launch
                 (N*d*4) over its average launch duration, from HIP events
                 attached to every pass launch on its stream (start and stop
-                of the kernel itself; a second timed run of the same step)
+                of the kernel itself; a second timed run of the same step);
+                `attainable` is the library's read probe on a buffer of the
+                bytes one pass reads (rows and D), re-read back to back
+  device        GPU name, architecture, compute units, HIP version
+  small         the 10,000 x 2, K=16 workload (latency-bound): us per
+                seeding run and per seeding + assignment step
   cpu_baseline  the FP64 oracle on the host cores, the same step on the
                 same rows (repeated to about 10 s of CPU work), same unit
   forms         the precision forms (BF16 / per-row FP8 rows) on the
@@ -380,6 +385,52 @@ def memory_spaces(kl, reps=3):
     return out
 
 
+def read_probe(kl, nbytes, reps=20):
+    """Attainable read bandwidth (GB/s) for a buffer of `nbytes` re-read back
+    to back, as the seed passes re-read the rows: the best over workgroup
+    counts and load kinds of the library's read probe."""
+    buf = torch.ones(nbytes // 16 * 4, dtype=torch.float32, device="cuda")
+    best, how = 0.0, None
+    for nt in (False, True):
+        for blocks in (2048, 4096, 8192, 16384):
+            out = torch.empty(blocks, dtype=torch.float32, device="cuda")
+            kl.kmpp_read_probe(buf, blocks=blocks, nontemporal=nt, out=out)
+            torch.cuda.synchronize()
+            ms = time_events(lambda: kl.kmpp_read_probe(buf, blocks=blocks, nontemporal=nt, out=out), reps)
+            gbs = buf.numel() * 4 / (ms * 1e-3) / 1e9
+            if gbs > best:
+                best, how = gbs, {"blocks": blocks, "nontemporal": nt}
+    del buf
+    return best, how
+
+
+def small_latency(kl, kmpp_synth, reps=50):
+    """The 10,000 x 2, K=16 workload: latency-bound, so microseconds per
+    seeding run and per seeding + assignment step."""
+    w = kmpp_synth.small(device="cuda")
+    X, K = w.X, w.K
+    idx = torch.empty(K, dtype=torch.int64, device="cuda")
+    C = torch.empty((K, w.d), dtype=torch.float32, device="cuda")
+    lab = torch.empty(w.N, dtype=torch.int32, device="cuda")
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(w.N, w.d, K), "cuda")
+    wa = kl.workspace(kl.kmpp_assign_workspace_bytes(w.N, w.d, K), "cuda")
+
+    def seed():
+        kl.kmpp_seed(X, K, 0, out_centers=C, out_idx=idx, ws=ws)
+
+    def step():
+        seed()
+        kl.kmpp_assign(X, C, out_labels=lab, ws=wa)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    seed_us = time_events(seed, reps) * 1e3
+    step_us = time_events(step, reps) * 1e3
+    return {"workload": f"small N={w.N} d={w.d} K={K}", "seed_us": seed_us, "step_us": step_us,
+            "status": kl.kmpp_status(ws)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +495,9 @@ def main():
 
     row_bytes = N * d * 4
     pass_ms, pass_gbs = seed_pass_rate(kl, X, K, row_bytes)
+    # the pass reads the rows and D (4 B per row), re-read pass after pass
+    probe_gbs, probe_how = read_probe(kl, row_bytes + 4 * N)
+    _log(f"read probe ({(row_bytes + 4 * N) / 1e6:.0f} MB re-read): {probe_gbs:.0f} GB/s {probe_how}")
     _log(f"seed pass avg {pass_ms * 1e3:.1f} us  {pass_gbs:.0f} GB/s")
     aflops = 2.0 * N * K * d
 
@@ -468,12 +522,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": pass_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "seed_pass_kernel<F32, d=32>", "avg_launch_us": pass_ms * 1e3,
-                     "bytes_per_launch": row_bytes},
+                     "bytes_per_launch": row_bytes, "attainable": probe_gbs,
+                     "frac_attainable": pass_gbs / probe_gbs, "attainable_probe": probe_how},
         "assign_roofline": {"bound": "mfma", "achieved": aflops / (assign_ms * 1e-3) / 1e12,
                             "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                             "frac": aflops / (assign_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"]},
     }
+    props = torch.cuda.get_device_properties(0)
+    res["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                     "compute_units": props.multi_processor_count, "hip": torch.version.hip}
     del ws, wa
+    res["small"] = small_latency(kl, kmpp_synth)
+    _log(f"small: seed {res['small']['seed_us']:.1f} us, step {res['small']['step_us']:.1f} us")
     if not args.no_forms:
         reps = 2
         forms = {}

@@ -98,7 +98,8 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
 /*
  * Where each draw runs (kmpp_seed_opts.draw).  Both follow the same steps
  * in the same order, so for one launch shape they pick the same seeds.
- *   KMPP_DRAW_AUTO    the tuning table's choice for (format, d), else PASS
+ *   KMPP_DRAW_AUTO    PASS where a pass has at most 256 tiles, else the
+ *                     tuning table's choice for (format, d), else KERNEL
  *   KMPP_DRAW_PASS    every workgroup of pass m+1 draws seed m at its start
  *                     from pass m's D and tile sums (one launch per seed;
  *                     passes then write D and tile sums to alternating
@@ -309,12 +310,26 @@ int kmpp_graph_launch(kmpp_graph g, void* stream);
 int kmpp_graph_destroy(kmpp_graph g);
 
 /* Tuning table: text lines
- * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <row path>]"
- * override the built-in choices for the seed pass; lines
+ * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <row path> [<draw>]]"
+ * override the built-in choices for the seed pass (draw: KMPP_DRAW_PASS or
+ * KMPP_DRAW_KERNEL); lines
  * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
  * alpha) set the batched planner's cost model.  Returns the number of
  * entries read or KMPP_E_INVALID. */
 int kmpp_tune_load(const char* path);
+
+/*
+ * Read-bandwidth probe (a measurement helper, not part of the method): reads
+ * `bytes` of device memory at `buf` once (grid-stride over `blocks`
+ * workgroups of 256 threads, 8 16-byte loads per lane in flight, cached or
+ * non-temporal loads) and writes the FP32 sum of the floats each workgroup
+ * read to out_partial[blocks] (device).  Timing it gives the attainable read
+ * bandwidth that the seed pass's rate is compared with.  buf 16-byte
+ * aligned, bytes a positive multiple of 16, 1 <= blocks <= 65536,
+ * nontemporal 0 or 1, else KMPP_E_INVALID.  Asynchronous on `stream`.
+ */
+int kmpp_read_probe(const void* buf, size_t bytes, int32_t blocks, int32_t nontemporal, float* out_partial,
+                    void* stream);
 
 const char* kmpp_strerror(int code);
 int kmpp_version(void);

@@ -37,7 +37,7 @@ SYMBOLS = [
     "kmpp_seed_parallel_workspace_bytes", "kmpp_seed_parallel",
     "kmpp_batched_workspace_bytes", "kmpp_seed_batched_prepare", "kmpp_seed_batched_launch",
     "kmpp_seed_batched", "kmpp_status", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
-    "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_strerror", "kmpp_version",
+    "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_read_probe", "kmpp_strerror", "kmpp_version",
 ]
 
 
@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
     L.kmpp_strerror.restype = ctypes.c_char_p
     L.kmpp_version.argtypes = []
     L.kmpp_version.restype = ctypes.c_int
+    L.kmpp_read_probe.argtypes = [P, sz, i32, i32, P, P]
+    L.kmpp_read_probe.restype = ctypes.c_int
     if os.path.exists(TUNE_PATH):
         L.kmpp_tune_load(TUNE_PATH.encode())
     _lib = L
@@ -360,3 +362,13 @@ def kmpp_tune_load(path: str) -> int:
 
 def kmpp_version() -> int:
     return int(lib().kmpp_version())
+
+
+def kmpp_read_probe(buf: torch.Tensor, blocks: int = 4096, nontemporal: bool = False, out=None, stream=None):
+    """Read-bandwidth probe (measurement helper): reads every byte of `buf`
+    once and returns the FP32 per-workgroup sums [blocks]."""
+    _require_cuda(buf)
+    out = torch.empty(blocks, dtype=torch.float32, device=buf.device) if out is None else out
+    _check(lib().kmpp_read_probe(_ptr(buf), buf.numel() * buf.element_size(), blocks, int(nontemporal), _ptr(out),
+                                 _stream(stream)), "kmpp_read_probe")
+    return out

@@ -40,6 +40,9 @@ bool tuned(int dtype, int d, SeedTune* t) {
 
 // Most tiles for the draw at pass start (every workgroup reads every tile sum).
 constexpr int kDrawAtStartTiles = 2048;
+// Up to this many tiles the automatic choice is the draw at pass start (it
+// was faster on every measured shape; with ~1000 tiles the draw kernel was).
+constexpr int kFewTiles = 256;
 
 // Rows larger than the 256 MiB last-level cache are streamed with
 // non-temporal loads; smaller ones stay cached between passes.
@@ -87,7 +90,7 @@ const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, int rl, in
 
 int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, const SeedVariant** var,
                      int* rpt_out, int* ntiles_out, int* draw_out) {
-  int nt = 256, rpt = 0, u = 8, draw = KMPP_DRAW_PASS;
+  int nt = 256, rpt = 0, u = 8, tuned_draw = 0;
   int ntl = (int64_t)N * d * elem_bytes(dtype) > kCachedRowBytes ? 1 : 0;
   SeedTune t;
   if (tuned(dtype, d, &t)) {
@@ -95,9 +98,8 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
     rpt = t.rpt;
     if (t.u > 0) u = t.u;
     if (t.ntl >= 0) ntl = t.ntl;
-    if (t.draw) draw = t.draw;
+    tuned_draw = t.draw;
   }
-  if (opts && opts->draw) draw = opts->draw;
   if (opts && opts->threads) nt = opts->threads;
   if (opts && opts->rows_per_tile > 0) rpt = opts->rows_per_tile;
   if (opts && opts->loads_per_lane > 0) u = opts->loads_per_lane;
@@ -123,6 +125,12 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   *var = v;
   *rpt_out = (int)r;
   *ntiles_out = (int)((N + r - 1) / r);
+  // the caller's choice; else the draw at pass start wherever a pass has few
+  // tiles (it saves a launch per seed and reads little), else the tuned
+  // choice (taken at one size per format and width), else the draw kernel
+  int draw = opts && opts->draw ? opts->draw : KMPP_DRAW_AUTO;
+  if (draw == KMPP_DRAW_AUTO)
+    draw = *ntiles_out <= kFewTiles ? KMPP_DRAW_PASS : (tuned_draw ? tuned_draw : KMPP_DRAW_KERNEL);
   *draw_out = draw;
   return KMPP_OK;
 }

@@ -84,6 +84,11 @@ def test_other_argument_checks_need_no_gpu(kl):
     assert L.kmpp_seed_batched(None, 3, 0, fake, 1 << 30, None) == -1
     assert L.kmpp_status(None, None, None) == -1
     assert L.kmpp_tune_load(b"/nonexistent/file") == -1
+    # read probe: size not a multiple of 16, no workgroups, bad load kind, null output
+    assert L.kmpp_read_probe(fake, 100, 4, 0, fake, None) == -1
+    assert L.kmpp_read_probe(fake, 1024, 0, 0, fake, None) == -1
+    assert L.kmpp_read_probe(fake, 1024, 4, 2, fake, None) == -1
+    assert L.kmpp_read_probe(fake, 1024, 4, 0, None, None) == -1
 
 
 def test_tune_file_parses(kl, tmp_path):
