@@ -129,6 +129,50 @@ def test_draw_at_pass_start_edge_cases(kl):
     assert np.all(D == 0.0)
 
 
+@pytest.mark.parametrize("draw", ["pass", "kernel"])
+def test_graph_capture_seed_and_assign(kl, draw):
+    # seeding + assignment captured into a HIP graph and replayed three
+    # times, outputs cleared eagerly between replays: every replay equals
+    # the eager run (the draw at pass start alternates buffers by pass, fixed
+    # per captured launch)
+    N, d, K = 150_001, 32, 40
+    Xh = kmpp_synth.gaussian(N, d, seed=15)
+    X = Xh.cuda()
+    dm = kl.KMPP_DRAW_PASS if draw == "pass" else kl.KMPP_DRAW_KERNEL
+    idx = torch.empty(K, dtype=torch.int64, device="cuda")
+    C = torch.empty((K, d), dtype=torch.float32, device="cuda")
+    D = torch.empty(N, dtype=torch.float32, device="cuda")
+    lab = torch.empty(N, dtype=torch.int32, device="cuda")
+    mind = torch.empty(N, dtype=torch.float32, device="cuda")
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, K), "cuda")
+    wa = kl.workspace(kl.kmpp_assign_workspace_bytes(N, d, K), "cuda")
+    s = torch.cuda.Stream()
+
+    def run():
+        kl.kmpp_seed(X, K, 8, out_centers=C, out_D=D, out_idx=idx, draw=dm, ws=ws)
+        kl.kmpp_assign(X, C, out_labels=lab, out_mind=mind, ws=wa)
+
+    with torch.cuda.stream(s):
+        run()
+    s.synchronize()
+    ref = [t.clone() for t in (idx, C, D, lab, mind)]
+    with torch.cuda.stream(s):
+        g = kl.Graph()
+        with g.capture():
+            run()
+    for rep in range(3):
+        for t in (idx, C, D, lab, mind):
+            t.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.launch()
+        s.synchronize()
+        assert kl.kmpp_status(ws) == 0
+        for a, b in zip((idx, C, D, lab, mind), ref):
+            assert torch.equal(a, b), f"replay {rep} differs"
+    check_seed_run(Xh.numpy(), K, 8, idx.cpu().numpy(), C.cpu().numpy(), D.cpu().numpy())
+
+
 def test_K1_and_K_equals_N(kl):
     Xh = kmpp_synth.gaussian(300, 5, seed=6)
     idx, C, D, st = run_seed(kl, Xh.cuda(), 1, seed=9)
