@@ -18,7 +18,10 @@ seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
   small         the 10,000 x 2, K=16 workload (latency-bound): us per
                 seeding run and per seeding + assignment step
   cpu_baseline  the FP64 oracle on the host cores, the same step on the
-                same rows (repeated to about 10 s of CPU work), same unit
+                same rows (repeated to about 10 s of CPU work), same unit;
+                cpu_baseline_1core: the oracle on one core, 16 seeds
+  ms_per_step_min / _median, cold_first_step_ms: per-step timings of the
+                same step (a second loop) and the process's first step
   forms         the precision forms (BF16 / per-row FP8 rows) on the
                 4,194,304 x 128 (K=1024) and 16,777,216 x 64 (K=4096)
                 workloads, and the batched form (512 uneven instances in one
@@ -168,6 +171,21 @@ def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 10.0, max_reps: int =
             "sample": f"the whole step on the same {N}x{Xh.shape[1]} rows (FP64 seeding, {K} passes: "
                       f"{np.mean(ts_seed):.2f} s; FP64 assignment of all rows: {np.mean(ts_assign):.2f} s), "
                       f"{len(times)} repetitions, {cores} threads"}
+
+
+def cpu_baseline_1core(Xh: np.ndarray, K: int = 16):
+    """The FP64 oracle on one core (the paper's CPU baseline is serial): the
+    same kind of step, K seeds on the same rows, value N*K per step-second."""
+    import oracle
+    N = Xh.shape[0]
+    t0 = time.perf_counter()
+    r = oracle.seed(Xh, K, seed=0, nthreads=1)
+    t1 = time.perf_counter()
+    oracle.assign(Xh, Xh[r.idx], nthreads=1)
+    t2 = time.perf_counter()
+    return {"value": N * K / (t2 - t0), "unit": "point-seed dists/s", "cores": 1, "kind": "oracle",
+            "sample": f"{K} seeds on the same {N}x{Xh.shape[1]} rows (FP64 seeding {t1 - t0:.2f} s, "
+                      f"assignment {t2 - t1:.2f} s), one thread"}
 
 
 def precision_forms(kl, name, w, reps):
@@ -483,11 +501,13 @@ def main():
         seed()
         assign()
 
+    cold_ms = time_events(step, 1)  # the first step of the process: code objects load here
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     ms = time_events(step, args.steps)
     torch.cuda.synchronize()
+    per_step = [time_events(step, 1) for _ in range(args.steps)]
     status = kl.kmpp_status(ws)
     seed_ms = time_events(seed, max(2, args.steps // 2))
     assign_ms = time_events(assign, max(2, args.steps // 2))
@@ -516,6 +536,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gaussian-mixture seeding + assignment, N=1000000 d=32 K=256 (256 components, "
                                "Dirichlet weights), FP32", "N": N, "d": d, "K": K},
+        "ms_per_step_min": float(np.min(per_step)),
+        "ms_per_step_median": float(np.median(per_step)),
+        "cold_first_step_ms": cold_ms,
         "seed_ms": seed_ms,
         "assign_ms": assign_ms,
         "seed_loop_GBps": row_bytes * K / (seed_ms * 1e-3) / 1e9,
@@ -564,7 +587,9 @@ def main():
     if not args.no_spaces:
         res["memory_spaces"] = memory_spaces(kl)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(X.cpu().numpy(), K)
+        Xh = X.cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline(Xh, K)
+        res["cpu_baseline_1core"] = cpu_baseline_1core(Xh)
     print(json.dumps(res), flush=True)
 
 
