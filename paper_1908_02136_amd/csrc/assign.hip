@@ -35,7 +35,7 @@ struct AssignParams {
   const int8_t* xexp;
   const float* C;       // [K, d] FP32
   const void* Cp;       // packed B fragments
-  float* cn;            // [Kp] ||c_j||^2 (FP32, direct)
+  float* cn;            // [Kp] -||c_j||^2 / 2 (FP32, direct; -inf for padding j >= K): each chain's start
   Ctl* ctl;             // status
   int32_t* flags;       // [N] queued rows
   int32_t* labels;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
         const float c = p.C[j * p.d + k];
         a = fmaf(c, c, a);
       }
-    p.cn[j] = a;
+    p.cn[j] = j < p.K ? -0.5f * a : -INFINITY;  // exact scaling
     if (j < p.K) atomicMax(reinterpret_cast<unsigned int*>(p.cmax2), __float_as_uint(a));
   }
   if (fmt == FMT_F32) {
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
   const int DQ = p.dp / 4;  // contraction elements per lane group
   const int Kt = p.Kp / 16;
   __shared__ uint4 sbuf[2][CHB / 16];
-  __shared__ uint4 scn[2][TPC * 4];  // ||c||^2 of the chunk's centres, 4 per entry
+  __shared__ uint4 scn[2][TPC * 4];  // chain starts -||c||^2 / 2 of the chunk's centres, 4 per entry
   __shared__ int s_nf;               // rows this workgroup queued for the recheck
 
   // first 16-row block of this wave; waves past the last block compute on
@@ -321,12 +321,9 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
     const int tn = min(TPC, Kt - c * TPC);
     // products of tile t into acc (the chain starts from -||c_j||^2 / 2)
     auto products = [&](int t, v4f(&acc)[RB]) {
-      const int j0 = (c * TPC + t) * 16 + 4 * q;  // this lane's first centre of the tile
-      const uint4 c4 = scn[c & 1][t * 4 + q];     // ||c||^2 of centres j0..j0+3 (padding: 0)
-      const v4f init = v4f{j0 < p.K ? -0.5f * __uint_as_float(c4.x) : -INFINITY,
-                           j0 + 1 < p.K ? -0.5f * __uint_as_float(c4.y) : -INFINITY,
-                           j0 + 2 < p.K ? -0.5f * __uint_as_float(c4.z) : -INFINITY,
-                           j0 + 3 < p.K ? -0.5f * __uint_as_float(c4.w) : -INFINITY};
+      const uint4 c4 = scn[c & 1][t * 4 + q];  // chain starts of this lane's centres j0..j0+3
+      const v4f init = v4f{__uint_as_float(c4.x), __uint_as_float(c4.y), __uint_as_float(c4.z),
+                           __uint_as_float(c4.w)};
       if constexpr (FMT == FMT_F32) {
         const float* bp = reinterpret_cast<const float*>(&sbuf[c & 1][0]) + (t * S) * 64 + lane;
 #pragma unroll
@@ -350,7 +347,10 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
           }
       }
     };
-    // running top-2 update with tile t's values
+    // running top-2 update with tile t's values: the new second is the
+    // median of (best, second, value); four VALU operations per value and
+    // no NaN canonicalisation (a NaN value leaves both unchanged: med3 then
+    // returns the smaller of best and second, and no comparison holds)
     auto epilogue = [&](int t, const v4f(&acc)[RB]) {
       const int j0 = (c * TPC + t) * 16 + 4 * q;
 #pragma unroll
@@ -358,9 +358,10 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float tv = acc[rb][v];
-          m2[rb] = fmaxf(m2[rb], fminf(m1[rb], tv));
-          i1[rb] = tv > m1[rb] ? j0 + v : i1[rb];
-          m1[rb] = fmaxf(m1[rb], tv);
+          m2[rb] = __builtin_amdgcn_fmed3f(m1[rb], m2[rb], tv);
+          const bool gt = tv > m1[rb];
+          i1[rb] = gt ? j0 + v : i1[rb];
+          m1[rb] = gt ? tv : m1[rb];
         }
     };
     for (int t = 0; t < tn; ++t) {
