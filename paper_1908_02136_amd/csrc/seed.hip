@@ -415,9 +415,23 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   const int64_t t0 = (int64_t)blockIdx.x * p.rows_per_tile;
   const int64_t t1 = min(p.N, t0 + (int64_t)p.rows_per_tile);
 
+  S st;
+  st.layout();
+  st.set_rows(p.xs, t0, t1, d);
+  // Narrow FP32 rows (at most 8 lanes per row), 512-thread workgroups,
+  // without DRAWER: this wave's first rows (and their D) are requested before
+  // the centre, so their latency overlaps the two dependent loads of the
+  // centre (its index, then its row); measured -1 to -3 % per seed for d = 2
+  // and 32.  Wider rows lose occupancy to the batch held meanwhile (+3 % at
+  // d = 128), with DRAWER the draw's registers come on top, and the 256-thread
+  // variants (those of the memory-space comparison) keep one code shape.
+  constexpr bool kEarly = !DRAWER && FMT == FMT_F32 && G <= 8 && NT == 512;
+  const int64_t base0 = t0 + (int64_t)st.wave * S::R;
+  typename S::Batch b0;
+  const bool early = kEarly && base0 < t1;
+  if (early) st.load(p, base0, t1, first, b0);
   // centre c_{pass-1}: the original FP32 row of the previous seed (drawn
-  // here first with DRAWER; loading this wave's first rows before the draw
-  // costs more occupancy than it hides latency)
+  // here first with DRAWER)
   int64_t cidx;
   if constexpr (DRAWER)
     cidx = p.pass >= 2 ? draw_at_start<NT>(p, cs) : p.idx[0];
@@ -425,8 +439,6 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     cidx = p.idx[p.pass - 1];
   const float* cg = p.X + cidx * (int64_t)d;
   const int64_t prev = (FMT != FMT_F32) ? cidx : -1;
-  S st;
-  st.layout();
   if constexpr (CS == CEN_SCALAR) {
     st.set_centre_uniform(cg);
   } else if constexpr (CS == CEN_GLOBAL) {
@@ -444,7 +456,6 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   // for weighted seeding, whose first centre comes from a draw)
   if (blockIdx.x == 0 && (p.pass > 1 || p.wts))
     for (int j = tid; j < d; j += NT) p.centers[(int64_t)(p.pass - 1) * d + j] = CS == CEN_LDS ? cs[j] : cg[j];
-  st.set_rows(p.xs, t0, t1, d);
 
   double acc = 0.0;
   float* D = p.D;
@@ -455,8 +466,12 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
       D[row] = dn;
     acc += p.wts ? (double)dn * (double)p.wts[row] : (double)dn;
   };
-  for (int64_t base = t0 + (int64_t)st.wave * S::R; base < t1; base += (int64_t)NW * S::R)
-    st.iter(p, base, t1, first, prev, sink);
+  for (int64_t base = base0; base < t1; base += (int64_t)NW * S::R) {
+    if (early && base == base0)
+      st.compute(base, t1, first, prev, b0, sink);
+    else
+      st.iter(p, base, t1, first, prev, sink);
+  }
 
   acc = wave_sum(acc);
   if ((tid & 63) == 0) red[st.wave] = acc;
