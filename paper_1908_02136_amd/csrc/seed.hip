@@ -1,7 +1,7 @@
 // seed.hip -- the k-means++ seed loop (paper, Section II, Algorithms 1-2).
 //
-// One launch per seed.  The pass kernel m (1..K) streams the point rows
-// once, updates every point's nearest squared distance
+// The pass kernel m (1..K) streams the point rows once, updates every
+// point's nearest squared distance
 // D = min(D, ||x - c_{m-1}||^2) and reduces D per workgroup tile into an FP64
 // tile sum.  For m < K seed m is then taken by inverting the FP64
 // cumulative distribution of D (tile sums, then the owning tile's rows) at
@@ -19,7 +19,8 @@
 // slice of its chunks in registers and the row distance is reduced across
 // the G lanes with xor shuffles.  U loads per lane are issued before any is
 // consumed.  D is read once per row per pass, 64 rows per coalesced
-// access, and written back only where it changed.
+// access, and written back only where it changed (every row, to the other
+// buffer, when the next pass draws at its start).
 #include <type_traits>
 
 #include "kmpp_dev.h"
@@ -406,7 +407,7 @@ template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, RL>;
   constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) float cs[];  // centre row, d floats (CEN_LDS); the drawer's staging
+  extern __shared__ __align__(16) float cs[];  // centre row, d floats (CEN_LDS); the draw's staging (DRAWER)
   __shared__ double red[NW];
 
   const int tid = threadIdx.x;
