@@ -57,6 +57,14 @@ struct LloydParams {
   double* cost;               // sum of mind, or null
   int32_t* counts_out;        // cluster sizes out, or null
   LloydCtl* lc;
+  int32_t Wc;                 // partial costs / changed counts to add in the finalize
+  // sorted path (see lloyd_hist_kernel)
+  int32_t Wh;                 // histogram workgroups; workgroup w takes rows [w * B, (w + 1) * B)
+  int64_t B;
+  int32_t CH;                 // sorted positions per run-sum workgroup
+  int32_t* hist;              // [K, Wh] rows of cluster j in block w, then their first position
+  int32_t* order;             // [N] row indices grouped by cluster
+  int32_t* coff;              // [K + 1] first sorted position of cluster j; coff[K] = rows with a label
 };
 
 template <int FMT>
@@ -219,17 +227,20 @@ __global__ __launch_bounds__(kLNT) void lloyd_accum_kernel(LloydParams p) {
     for (int q0 = 0; q0 < nm; q0 += rpw * U) {
       float v[U][EPL];
       int jr[U];
+      // unconditional loads (row and element clamped into range, values
+      // masked afterwards): all of them in flight together
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int slot = q0 + u * rpw + rg;
         const bool ok = slot < nm;
         const int pk = ok ? s_pk[wave][slot] : -1;
-        const int64_t rr = base + (pk & 255);
+        const int64_t rr = min(p.N - 1, base + (pk & 255));
         jr[u] = ok ? (pk >> 8) : -1;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           const int k = sub + G * e;
-          v[u][e] = (ok && k < p.d) ? lx<FMT>(p, rr, k) : 0.0f;
+          const float x = lx<FMT>(p, rr, k < p.d ? k : p.d - 1);
+          v[u][e] = (ok && k < p.d) ? x : 0.0f;
         }
       }
 #pragma unroll
@@ -300,11 +311,11 @@ __global__ __launch_bounds__(256) void lloyd_finalize_kernel(LloydParams p) {
     if (p.counts_out && e % p.d == 0) p.counts_out[j] = n;
   }
   if (blockIdx.x == 0) {
-    const int per = (p.W + 255) / 256;
+    const int per = (p.Wc + 255) / 256;
     const int b0 = threadIdx.x * per;
     double s = 0.0;
     unsigned long long c = 0;
-    for (int i = b0; i < min(p.W, b0 + per); ++i) {
+    for (int i = b0; i < min(p.Wc, b0 + per); ++i) {
       s += p.pcost[i];
       c += p.pchg[i];
     }
@@ -323,6 +334,202 @@ __global__ __launch_bounds__(256) void lloyd_finalize_kernel(LloydParams p) {
   }
 }
 
+// ---------------------------------------------------------------- sorted path
+// With many cluster ranges (large K * d) the LDS path re-reads the labels
+// once per range and adds every element with an LDS atomic.  The sorted
+// path groups the rows by label instead (a counting sort: per-block label
+// histograms, per-cluster positions, a scatter of row indices), then each
+// run-sum workgroup adds contiguous runs of one cluster's rows in registers
+// and each run's fixed-point sums into the cluster's sums with one 64-bit
+// integer atomic per element.  Integer additions do not depend on their
+// order, so the centres are the same bits as on the LDS path; the cost and
+// the changed-label count are added per block in a fixed order.
+constexpr int kSNT = 256;  // threads of the sorted-path kernels
+
+// Block w: label histogram (LDS) of rows [w * B, (w + 1) * B), written to
+// hist[j * Wh + w], and the block's cost and changed count.
+__global__ __launch_bounds__(kSNT) void lloyd_hist_kernel(LloydParams p) {
+  extern __shared__ int sh_h[];  // [K]
+  __shared__ double red[kSNT / 64];
+  __shared__ unsigned int red_c[kSNT / 64];
+  const int tid = threadIdx.x, w = blockIdx.x;
+  for (int j = tid; j < p.K; j += kSNT) sh_h[j] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)w * p.B, r1 = min(p.N, r0 + p.B);
+  double cost = 0.0;
+  unsigned int ch = 0;
+  for (int64_t r = r0 + tid; r < r1; r += kSNT) {
+    const int lab = p.labels[r];
+    if ((unsigned)lab < (unsigned)p.K) {  // -1: a row with NaN, in no cluster
+      atomicAdd(&sh_h[lab], 1);
+      cost += (double)p.mind[r];
+      ch += p.prev ? (p.prev[r] != lab) : 1u;
+    }
+  }
+  cost = wave_sum(cost);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ch += __shfl_xor(ch, o, 64);
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = cost;
+    red_c[tid >> 6] = ch;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    p.pcost[w] = ((red[0] + red[1]) + red[2]) + red[3];
+    p.pchg[w] = red_c[0] + red_c[1] + red_c[2] + red_c[3];
+  }
+  for (int j = tid; j < p.K; j += kSNT) p.hist[(int64_t)j * p.Wh + w] = sh_h[j];
+}
+
+// One wave per cluster: exclusive prefix of its block counts (in place) and
+// its size.
+__global__ __launch_bounds__(kSNT) void lloyd_cscan_kernel(LloydParams p) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (kSNT / 64) + (threadIdx.x >> 6);
+  if (j >= p.K) return;  // whole waves; no barriers below
+  int32_t* h = p.hist + (int64_t)j * p.Wh;
+  int run = 0;
+  for (int w0 = 0; w0 < p.Wh; w0 += 64) {
+    const int w = w0 + lane;
+    const int v = w < p.Wh ? h[w] : 0;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (w < p.Wh) h[w] = run + x - v;
+    run += __shfl(x, 63, 64);
+  }
+  if (lane == 0) p.pcnt[j] = run;
+}
+
+// One workgroup: coff = exclusive prefix of the cluster sizes.
+__global__ __launch_bounds__(1024) void lloyd_oscan_kernel(LloydParams p) {
+  __shared__ int sh[1024];
+  const int per = (p.K + 1023) / 1024;
+  const int b0 = min(p.K, (int)threadIdx.x * per), b1 = min(p.K, b0 + per);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += p.pcnt[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+    p.coff[p.K] = run;
+  }
+  __syncthreads();
+  int off = sh[threadIdx.x];
+  for (int i = b0; i < b1; ++i) {
+    p.coff[i] = off;
+    off += p.pcnt[i];
+  }
+}
+
+// Block w: row r with label j goes to order[coff[j] + hist[j][w] + its rank
+// among the block's rows of cluster j] (the rank order is arbitrary; the sums
+// do not depend on it).
+__global__ __launch_bounds__(kSNT) void lloyd_scatter_kernel(LloydParams p) {
+  extern __shared__ int cur[];  // [K]
+  const int tid = threadIdx.x, w = blockIdx.x;
+  for (int j = tid; j < p.K; j += kSNT) cur[j] = p.coff[j] + p.hist[(int64_t)j * p.Wh + w];
+  __syncthreads();
+  const int64_t r0 = (int64_t)w * p.B, r1 = min(p.N, r0 + p.B);
+  for (int64_t r = r0 + tid; r < r1; r += kSNT) {
+    const int lab = p.labels[r];
+    if ((unsigned)lab < (unsigned)p.K) p.order[atomicAdd(&cur[lab], 1)] = (int32_t)r;
+  }
+}
+
+__global__ __launch_bounds__(kSNT) void lloyd_zero_kernel(long long* a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kSNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSNT) a[i] = 0;
+}
+
+// Workgroup c: sorted positions [c * CH, (c + 1) * CH) cut into runs of one
+// cluster; the four waves take every fourth row of a run with lanes over
+// the elements (DPL per lane, d <= 64 * DPL) and kRU rows in flight (the
+// next rows' indices load with the current rows), the run's sums meet in
+// LDS and go to sums[j] (pacc) with integer atomics.
+constexpr int kRU = 8;
+template <int FMT, int DPL>
+__global__ __launch_bounds__(kSNT) void lloyd_runsum_kernel(LloydParams p) {
+  __shared__ long long part[kSNT / 64 - 1][64 * DPL];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = p.coff[p.K];
+  const int64_t s0 = (int64_t)blockIdx.x * p.CH;
+  if (s0 >= M) return;  // uniform over the workgroup
+  const int64_t s1 = min((int64_t)M, s0 + p.CH);
+  // the last cluster starting at or before s0 (it holds s0: s0 < coff[K])
+  int lo = 0, hi = p.K - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p.coff[mid] <= s0)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int j = lo;
+  const int F = lloyd_F(p);
+  int64_t s = s0;
+  while (s < s1) {
+    const int64_t e = min(s1, (int64_t)p.coff[j + 1]);
+    long long acc[DPL];
+#pragma unroll
+    for (int i = 0; i < DPL; ++i) acc[i] = 0;
+    constexpr int64_t kStep = (int64_t)(kSNT / 64) * kRU;
+    // every load is unconditional (indices clamped into range, values
+    // masked afterwards), so a wave's loads are all in flight together
+    int64_t nrow[kRU];
+#pragma unroll
+    for (int u = 0; u < kRU; ++u) {
+      const int64_t q = s + wave + (int64_t)u * (kSNT / 64);
+      nrow[u] = p.order[q < e ? q : e - 1];
+    }
+    for (int64_t q0 = s + wave; q0 < e; q0 += kStep) {
+      int64_t row[kRU];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) {
+        row[u] = nrow[u];
+        const int64_t q = q0 + kStep + (int64_t)u * (kSNT / 64);
+        nrow[u] = p.order[q < e ? q : e - 1];
+      }
+      float v[kRU][DPL];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u)
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) {
+          const int k = lane + 64 * i;
+          const float x = lx<FMT>(p, row[u], k < p.d ? k : p.d - 1);
+          v[u][i] = (q0 + (int64_t)u * (kSNT / 64) < e && k < p.d) ? x : 0.0f;
+        }
+#pragma unroll
+      for (int u = 0; u < kRU; ++u)
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) acc[i] += __float2ll_rn(ldexpf(v[u][i], F));
+    }
+    if (wave > 0)
+#pragma unroll
+      for (int i = 0; i < DPL; ++i) part[wave - 1][lane + 64 * i] = acc[i];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int i = 0; i < DPL; ++i) {
+        const int k = lane + 64 * i;
+        const long long t = acc[i] + part[0][lane + 64 * i] + part[1][lane + 64 * i] + part[2][lane + 64 * i];
+        if (k < p.d && t != 0)
+          atomicAdd(reinterpret_cast<unsigned long long*>(p.pacc + (int64_t)j * p.d + k), (unsigned long long)t);
+      }
+    __syncthreads();  // part is rewritten by the next run
+    s = e;
+    ++j;
+    while (j < p.K && (int64_t)p.coff[j + 1] <= s) ++j;  // empty clusters
+  }
+}
+
 // ---------------------------------------------------------------- host
 namespace {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -333,8 +540,17 @@ constexpr int64_t kTargetWG = 512;           // two workgroups per CU (LDS-bound
 
 struct LloydPlan {
   int G, lgG, R, Kr, W;
-  int epl;  // elements per lane per row: a power of two with G * epl >= d
+  int epl;      // elements per lane per row: a power of two with G * epl >= d
+  bool sorted;  // the sorted path (many cluster ranges)
+  int Wh, CH, dpl;
+  int64_t B;
 };
+
+// The sorted path from this many cluster ranges on (K <= 15360 for its LDS
+// histograms within 64 KiB, d <= 512 for its registers).
+constexpr int kSortedRanges = 4;
+constexpr int kSortedMaxK = 15360;
+constexpr int kSortedMaxD = 512;
 
 LloydPlan lloyd_plan(int64_t N, int d, int K) {
   LloydPlan P;
@@ -350,6 +566,13 @@ LloydPlan lloyd_plan(int64_t N, int d, int K) {
   P.W = (int)std::max<int64_t>(1, std::min<int64_t>(steps, kTargetWG / P.R));
   P.epl = 1;
   while (P.epl * P.G < d) P.epl <<= 1;
+  P.sorted = P.R >= kSortedRanges && K <= kSortedMaxK && d <= kSortedMaxD;
+  P.Wh = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (N + 4095) / 4096));
+  P.B = (N + P.Wh - 1) / P.Wh;
+  P.CH = 2048;
+  P.dpl = 1;
+  while (P.dpl * 64 < d) P.dpl <<= 1;
+  if (P.sorted) P.W = 1;  // one set of sums, added to with integer atomics
   return P;
 }
 
@@ -373,8 +596,43 @@ hipError_t launch_accum(const LloydParams& p, int epl, unsigned grid, size_t shm
   }
 }
 
+template <int FMT, int DPL>
+hipError_t launch_runsum_e(const LloydParams& p, unsigned grid, hipStream_t s) {
+  hipLaunchKernelGGL((lloyd_runsum_kernel<FMT, DPL>), dim3(grid), dim3(kSNT), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_runsum(const LloydParams& p, int dpl, unsigned grid, hipStream_t s) {
+  switch (dpl) {
+    case 1: return launch_runsum_e<FMT, 1>(p, grid, s);
+    case 2: return launch_runsum_e<FMT, 2>(p, grid, s);
+    case 4: return launch_runsum_e<FMT, 4>(p, grid, s);
+    case 8: return launch_runsum_e<FMT, 8>(p, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One iteration's sums on the sorted path: histograms, positions, scatter,
+// zeroed sums, run sums.
+hipError_t launch_sorted(const LloydParams& p, const LloydPlan& P, int dtype, hipStream_t s) {
+  const size_t hsh = sizeof(int) * (size_t)p.K;
+  const int64_t kd = (int64_t)p.K * p.d;
+  hipLaunchKernelGGL(lloyd_hist_kernel, dim3((unsigned)P.Wh), dim3(kSNT), hsh, s, p);
+  hipLaunchKernelGGL(lloyd_cscan_kernel, dim3((unsigned)((p.K + kSNT / 64 - 1) / (kSNT / 64))), dim3(kSNT), 0, s, p);
+  hipLaunchKernelGGL(lloyd_oscan_kernel, dim3(1), dim3(1024), 0, s, p);
+  hipLaunchKernelGGL(lloyd_scatter_kernel, dim3((unsigned)P.Wh), dim3(kSNT), hsh, s, p);
+  hipLaunchKernelGGL(lloyd_zero_kernel, dim3((unsigned)std::min<int64_t>(1024, (kd + kSNT - 1) / kSNT)), dim3(kSNT), 0,
+                     s, p.pacc, kd);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  const unsigned grid = (unsigned)((p.N + P.CH - 1) / P.CH);
+  if (dtype == KMPP_F32) return launch_runsum<FMT_F32>(p, P.dpl, grid, s);
+  if (dtype == KMPP_BF16) return launch_runsum<FMT_BF16>(p, P.dpl, grid, s);
+  return launch_runsum<FMT_FP8>(p, P.dpl, grid, s);
+}
+
 struct LloydLayout {
-  size_t assign, mind, labels, pacc, pcnt, pcost, pchg, pamax, changed, total;
+  size_t assign, mind, labels, pacc, pcnt, pcost, pchg, pamax, changed, hist, order, coff, total;
 };
 
 LloydLayout lloyd_layout(int64_t N, int d, int K, int dtype) {
@@ -391,14 +649,24 @@ LloydLayout lloyd_layout(int64_t N, int d, int K, int dtype) {
   off += a256(sizeof(long long) * (size_t)P.W * (size_t)K * (size_t)d);
   L.pcnt = off;
   off += a256(sizeof(int32_t) * (size_t)P.W * (size_t)K);
+  const size_t nparts = (size_t)std::max(P.W, P.sorted ? P.Wh : 1);
   L.pcost = off;
-  off += a256(sizeof(double) * (size_t)P.W);
+  off += a256(sizeof(double) * nparts);
   L.pchg = off;
-  off += a256(sizeof(uint32_t) * (size_t)P.W);
+  off += a256(sizeof(uint32_t) * nparts);
   L.pamax = off;
   off += a256(sizeof(float) * kMaxAmaxWG);
   L.changed = off;
   off += 256;
+  L.hist = L.order = L.coff = off;
+  if (P.sorted) {
+    L.hist = off;
+    off += a256(sizeof(int32_t) * (size_t)K * (size_t)P.Wh);
+    L.order = off;
+    off += a256(sizeof(int32_t) * (size_t)N);
+    L.coff = off;
+    off += a256(sizeof(int32_t) * ((size_t)K + 1));
+  }
   L.total = off;
   return L;
 }
@@ -437,6 +705,14 @@ int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d
   p.changed = nullptr;
   p.cost = nullptr;
   p.counts_out = nullptr;
+  p.Wc = P.W;
+  p.Wh = P.Wh;
+  p.B = P.B;
+  p.CH = P.CH;
+  p.hist = reinterpret_cast<int32_t*>(w + L.hist);
+  p.order = reinterpret_cast<int32_t*>(w + L.order);
+  p.coff = reinterpret_cast<int32_t*>(w + L.coff);
+  if (P.sorted) p.Wc = P.Wh;
 
   const size_t shmem = (size_t)P.Kr * ((size_t)d * 8 + 4);
   const int64_t kd = (int64_t)K * d;
@@ -473,12 +749,15 @@ int launch_lloyd(const void* X, const int8_t* X_exp, int dtype, int64_t N, int d
     p.cost = out_cost ? out_cost + t : nullptr;
     p.counts_out = t == iters - 1 ? out_counts : nullptr;
     hipError_t e;
-    if (dtype == KMPP_F32)
+    if (P.sorted) {
+      e = launch_sorted(p, P, dtype, stream);
+    } else if (dtype == KMPP_F32) {
       e = launch_accum<FMT_F32>(p, P.epl, grid, shmem, stream);
-    else if (dtype == KMPP_BF16)
+    } else if (dtype == KMPP_BF16) {
       e = launch_accum<FMT_BF16>(p, P.epl, grid, shmem, stream);
-    else
+    } else {
       e = launch_accum<FMT_FP8>(p, P.epl, grid, shmem, stream);
+    }
     if (e != hipSuccess) return KMPP_E_HIP;
     hipLaunchKernelGGL(lloyd_finalize_kernel, dim3(fin_grid), dim3(256), 0, stream, p);
     if (hipGetLastError() != hipSuccess) return KMPP_E_HIP;

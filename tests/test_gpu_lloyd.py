@@ -111,9 +111,11 @@ def test_lloyd_lattice_first_update_bit_exact(kl, d):
     assert int(ch[0]) == int(ch_or[0]) == N
 
 
-@pytest.mark.parametrize("d,K", [(5, 40), (17, 300), (64, 256), (100, 20), (300, 9)])
+@pytest.mark.parametrize("d,K", [(5, 40), (17, 300), (64, 256), (100, 20), (300, 9),
+                                 (128, 1024), (33, 2000), (512, 100), (64, 1000)])
 def test_lloyd_shapes_and_paths(kl, d, K):
-    # K*d*8 bytes above 60 KiB takes the global-atomic path, below the LDS one
+    # the cluster sums of one LDS range hold about 47 KiB: up to 3 ranges the
+    # LDS path, from 4 ranges on (the last four shapes) the sorted path
     N = 30_011
     Xh = kmpp_synth.gaussian(N, d, seed=700 + d)
     X = Xh.cuda()
@@ -143,6 +145,20 @@ def test_lloyd_precision_forms(kl, fmt):
     _say(fmt, N, d, K)
     idx, C0, _, _ = kl.kmpp_seed(X, K, 2, Xq=Xq, Xq_exp=E, dtype=dt)
     replay(kl, Xq, Xd, C0, 3, X_exp=E, dtype=dt)
+
+
+def test_lloyd_sorted_path_determinism(kl):
+    # the sorted path's scatter order varies from run to run; the integer
+    # sums do not, so two runs give the same bits
+    N, d, K = 50_021, 128, 1024
+    Xh = kmpp_synth.gaussian(N, d, seed=901)
+    X = Xh.cuda()
+    idx, C0, _, _ = kl.kmpp_seed(X, K, 2)
+    _say("sorted path determinism", N, d, K)
+    outs = [kl.kmpp_lloyd(X, C0.clone(), 3) for _ in range(2)]
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0][:5], outs[1][:5]):
+        assert torch.equal(a, b)
 
 
 def test_lloyd_determinism_and_empty_clusters(kl):
