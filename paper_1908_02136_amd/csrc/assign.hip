@@ -36,8 +36,7 @@ struct AssignParams {
   const float* C;       // [K, d] FP32
   const void* Cp;       // packed B fragments
   float* cn;            // [Kp] -||c_j||^2 / 2 (FP32, direct; -inf for padding j >= K): each chain's start
-  Ctl* ctl;             // status
-  int32_t* flags;       // [N] queued rows
+  Ctl* ctl;             // status; nflag counts the rows queued for the recheck
   int32_t* labels;
   float* mind;
   float* cmax2;         // max_j ||c_j||^2 (workspace scalar)
@@ -47,11 +46,7 @@ struct AssignParams {
   int32_t all_rows;     // recheck kernel: every row instead of the queue
   float* Ct;            // [d, Kq] the centres transposed (zero past K)
   int32_t Kq;           // K rounded up to 64
-  int32_t* fcnt;        // [nseg] rows queued by main-kernel workgroup b (segment b of flags)
-  int32_t* foff;        // [nseg] their offsets in the compacted queue
-  int32_t* cflags;      // [N] the compacted queue
-  int32_t seg;          // rows per segment (= rows per main-kernel workgroup)
-  int32_t nseg;         // segments (main-kernel workgroups)
+  int32_t* cflags;      // [N] the rows queued for the recheck (nflag of them)
 };
 
 // ---- per-format row fragment handling
@@ -111,11 +106,13 @@ __device__ __forceinline__ float x_at<FMT_FP8>(const AssignParams& p, int64_t ro
 //       DQ = dp/4 (steps per lane group), s < DQ.
 // BF16: Cp[jt][h][s][lane] = 8 BF16 of part h (0 high, 1 remainder) of
 //       C[16 jt + lane%16][q*DQ + 8 s + 0..7], DQ = dp/4, s < DQ/8.
-__global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fmt) {
+// A thread takes items tid, tid + stride, ...; it returns the bits of the
+// largest ||c_j||^2 it saw (as unsigned integers non-negative floats order
+// like their values, and NaN above them).
+__device__ uint32_t prep_part(const AssignParams& p, int fmt, int64_t tid, int64_t stride) {
   const int Kt = p.Kp / 16;
   const int DQ = p.dp / 4;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t mx = 0u;
   for (int64_t j = tid; j < p.Kp; j += stride) {
     float a = 0.0f;
     if (j < p.K)
@@ -124,7 +121,7 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
         a = fmaf(c, c, a);
       }
     p.cn[j] = j < p.K ? -0.5f * a : -INFINITY;  // exact scaling
-    if (j < p.K) atomicMax(reinterpret_cast<unsigned int*>(p.cmax2), __float_as_uint(a));
+    if (j < p.K) mx = max(mx, __float_as_uint(a));
   }
   if (fmt == FMT_F32) {
     float* Cp = (float*)const_cast<void*>(p.Cp);
@@ -156,6 +153,12 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
       Cp[e] = (uint16_t)(h == 0 ? hi : lo);
     }
   }
+  return mx;
+}
+
+__global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fmt) {
+  const uint32_t mx = prep_part(p, fmt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+  if (mx) atomicMax(reinterpret_cast<unsigned int*>(p.cmax2), mx);
 }
 
 // ---------------------------------------------------------------- main
@@ -173,8 +176,13 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
 // the accumulator -||c_j||^2 / 2, so the running value is
 // t = <x, c_j> - ||c_j||^2 / 2 = -score / 2 and the per-pair work is the
 // top-2 update alone (largest t, ties to the smaller index).
+// Waves per SIMD the compiler must allow: FP32 rows of width 97..128 fit 128
+// registers, so four waves (measured faster than three); no constraint otherwise.
+constexpr int assign_min_waves(int fmt, int dqk) { return fmt == FMT_F32 && dqk == 32 ? 4 : 1; }
+
 template <int FMT, int DQK, int RB>
-__global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(assign_min_waves(FMT, DQK))))
+void assign_mfma_kernel(AssignParams p) {
   using F = Frag<FMT>;
   constexpr bool BF = FMT != FMT_F32;
   constexpr int S = DQK;                                 // MFMA steps per centre tile (per product)
@@ -190,7 +198,9 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
   const int Kt = p.Kp / 16;
   __shared__ uint4 sbuf[2][CHB / 16];
   __shared__ uint4 scn[2][TPC * 4];  // chain starts -||c||^2 / 2 of the chunk's centres, 4 per entry
-  __shared__ int s_nf;               // rows this workgroup queued for the recheck
+  __shared__ int s_nf;               // rows this workgroup queued for the recheck ...
+  __shared__ int s_q[4 * RB * 16];   // ... and their indices
+  __shared__ int s_base;             // where they go in the queue
 
   // first 16-row block of this wave; waves past the last block compute on
   // clamped rows and store nothing (they still take part in the barriers)
@@ -440,19 +450,23 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
       p.labels[row] = best;
       if (p.mind) p.mind[row] = dd;
     }
-    // rows for the recheck go to this workgroup's segment of the queue (an
-    // LDS counter; no global atomics)
+    // rows for the recheck are collected in LDS
     const bool flag = mine && !sure;
     const unsigned long long fm = __ballot(flag);
     if (fm) {
       int base = 0;
       if (lane == 0) base = atomicAdd(&s_nf, __popcll(fm));
       base = __shfl(base, 0, 64);
-      if (flag) p.flags[(int64_t)blockIdx.x * p.seg + base + __popcll(fm & ((1ull << lane) - 1ull))] = (int32_t)row;
+      if (flag) s_q[base + __popcll(fm & ((1ull << lane) - 1ull))] = (int32_t)row;
     }
   }
+  // ... and appended to the queue at a range reserved with one atomic per
+  // workgroup (the queue's order does not matter: each row's recheck is
+  // independent of the others)
   __syncthreads();
-  if (tid == 0) p.fcnt[blockIdx.x] = s_nf;
+  if (tid == 0) s_base = s_nf ? (int)atomicAdd(&p.ctl->nflag, (uint32_t)s_nf) : 0;
+  __syncthreads();
+  for (int i = tid; i < s_nf; i += 256) p.cflags[s_base + i] = s_q[i];
 }
 
 // ---------------------------------------------------------------- recheck
@@ -463,12 +477,16 @@ __global__ __launch_bounds__(256) void assign_mfma_kernel(AssignParams p) {
 // value serves all kRR rows, whose values are the same for all lanes.
 constexpr int kRR = 8;
 
-__global__ __launch_bounds__(256) void assign_transpose_kernel(AssignParams p) {
+__device__ void transpose_part(const AssignParams& p, int64_t tid, int64_t stride) {
   const int64_t total = (int64_t)p.d * p.Kq;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+  for (int64_t e = tid; e < total; e += stride) {
     const int64_t k = e / p.Kq, j = e % p.Kq;
     p.Ct[e] = j < p.K ? p.C[j * p.d + k] : 0.0f;
   }
+}
+
+__global__ __launch_bounds__(256) void assign_transpose_kernel(AssignParams p) {
+  transpose_part(p, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
 }
 
 // A workgroup takes kRR rows at once and its four waves split the centres
@@ -590,55 +608,43 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
   }
 }
 
-// The queue segments of the main kernel's workgroups, compacted in
-// workgroup order: one workgroup scans the counts (fixed order) ...
-__global__ __launch_bounds__(1024) void assign_qscan_kernel(AssignParams p) {
-  __shared__ int sh[1024];
-  const int per = (p.nseg + 1023) / 1024;
-  const int b0 = threadIdx.x * per;
-  int s = 0;
-  for (int i = b0; i < min(p.nseg, b0 + per); ++i) s += p.fcnt[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const int v = sh[i];
-      sh[i] = run;
-      run += v;
-    }
-    p.ctl->nflag = (uint32_t)run;
-  }
-  __syncthreads();
-  int off = sh[threadIdx.x];
-  for (int i = b0; i < min(p.nseg, b0 + per); ++i) {
-    p.foff[i] = off;
-    off += p.fcnt[i];
-  }
-}
-
-// ... and every segment is copied to its offset.
-__global__ __launch_bounds__(256) void assign_qcopy_kernel(AssignParams p) {
-  for (int64_t sg = blockIdx.x; sg < p.nseg; sg += gridDim.x) {
-    const int n = p.fcnt[sg];
-    const int o = p.foff[sg];
-    for (int i = threadIdx.x; i < n; i += 256) p.cflags[o + i] = p.flags[sg * (int64_t)p.seg + i];
-  }
-}
-
 __global__ void assign_reset_kernel(Ctl* ctl, float* cmax2) {
   ctl->status = KMPP_OK;
-
+  ctl->nflag = 0u;
   *cmax2 = 0.0f;
+}
+
+// Small centre sets: the reset, the transposed copy, the chain starts and
+// the packed fragments in one workgroup (one launch instead of three).
+__global__ __launch_bounds__(1024) void assign_setup_kernel(AssignParams p, int fmt) {
+  __shared__ uint32_t smx[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    p.ctl->status = KMPP_OK;
+    p.ctl->nflag = 0u;
+  }
+  transpose_part(p, tid, 1024);
+  uint32_t mx = prep_part(p, fmt, tid, 1024);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  if (lane == 0) smx[wave] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t m = 0u;
+    for (int w = 0; w < 16; ++w) m = max(m, smx[w]);
+    *reinterpret_cast<uint32_t*>(p.cmax2) = m;
+  }
 }
 
 // ---------------------------------------------------------------- host
 namespace {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+// padded centre elements (Kp * dp) up to which one workgroup prepares the centres
+constexpr int64_t kSetupOneWg = 1 << 16;
 
 struct AssignLayout {
-  size_t cn, cmax, cp, ct, flags, fcnt, foff, cflags, total;
+  size_t cn, cmax, cp, ct, cflags, total;
   int Kp, dp, Kq;
 };
 
@@ -667,12 +673,6 @@ AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   L.Kq = round_up(K, 64);
   L.ct = off;
   off += a256(sizeof(float) * (size_t)L.Kq * (size_t)d);
-  L.flags = off;
-  off += a256(sizeof(int32_t) * (size_t)(N + 256));
-  L.fcnt = off;
-  off += a256(sizeof(int32_t) * (size_t)(N / 64 + 2));
-  L.foff = off;
-  off += a256(sizeof(int32_t) * (size_t)(N / 64 + 2));
   L.cflags = off;
   off += a256(sizeof(int32_t) * (size_t)N);
   L.total = off;
@@ -683,8 +683,6 @@ template <int FMT, int DQK, int RB>
 hipError_t launch_main(AssignParams& p, hipStream_t stream) {
   const int64_t waves = (p.nblk + RB - 1) / RB;
   const int64_t blocks = (waves + 3) / 4;
-  p.seg = 4 * RB * 16;  // one recheck-queue segment per workgroup
-  p.nseg = (int)blocks;
   hipLaunchKernelGGL((assign_mfma_kernel<FMT, DQK, RB>), dim3((unsigned)blocks), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
@@ -737,7 +735,6 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.Cp = w + L.cp;
   p.cn = reinterpret_cast<float*>(w + L.cn);
   p.ctl = reinterpret_cast<Ctl*>(w);
-  p.flags = reinterpret_cast<int32_t*>(w + L.flags);
   p.labels = labels;
   p.mind = mind;
   p.cmax2 = reinterpret_cast<float*>(w + L.cmax);
@@ -749,19 +746,19 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.nblk = (int)((N + 15) / 16);
   p.Ct = reinterpret_cast<float*>(w + L.ct);
   p.Kq = L.Kq;
-  p.fcnt = reinterpret_cast<int32_t*>(w + L.fcnt);
-  p.foff = reinterpret_cast<int32_t*>(w + L.foff);
   p.cflags = reinterpret_cast<int32_t*>(w + L.cflags);
-  p.seg = 256;  // all-rows mode; the main kernel's launch sets its own
-  p.nseg = (int)((N + 255) / 256);
 
   p.all_rows = 0;
 
-  hipLaunchKernelGGL(assign_reset_kernel, dim3(1), dim3(1), 0, stream, p.ctl, p.cmax2);
-  hipLaunchKernelGGL(assign_transpose_kernel, dim3(256), dim3(256), 0, stream, p);
   const int steps = assign_steps(d, dtype);
+  if (steps && (int64_t)L.Kp * L.dp <= kSetupOneWg) {
+    hipLaunchKernelGGL(assign_setup_kernel, dim3(1), dim3(1024), 0, stream, p, dtype);
+  } else {
+    hipLaunchKernelGGL(assign_reset_kernel, dim3(1), dim3(1), 0, stream, p.ctl, p.cmax2);
+    hipLaunchKernelGGL(assign_transpose_kernel, dim3(256), dim3(256), 0, stream, p);
+    if (steps) hipLaunchKernelGGL(assign_prep_kernel, dim3(256), dim3(256), 0, stream, p, dtype);
+  }
   if (steps) {
-    hipLaunchKernelGGL(assign_prep_kernel, dim3(256), dim3(256), 0, stream, p, dtype);
     hipError_t e;
     if (dtype == KMPP_F32)
       e = dispatch_main<FMT_F32>(p, steps, stream);
@@ -770,8 +767,6 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
     else
       e = dispatch_main<FMT_FP8>(p, steps, stream);
     if (e != hipSuccess) return KMPP_E_HIP;
-    hipLaunchKernelGGL(assign_qscan_kernel, dim3(1), dim3(1024), 0, stream, p);
-    hipLaunchKernelGGL(assign_qcopy_kernel, dim3(1024), dim3(256), 0, stream, p);
   } else {
     p.all_rows = 1;  // wider than the MFMA path: every row in the direct form
   }
