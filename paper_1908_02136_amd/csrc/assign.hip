@@ -106,58 +106,97 @@ __device__ __forceinline__ float x_at<FMT_FP8>(const AssignParams& p, int64_t ro
 //       DQ = dp/4 (steps per lane group), s < DQ.
 // BF16: Cp[jt][h][s][lane] = 8 BF16 of part h (0 high, 1 remainder) of
 //       C[16 jt + lane%16][q*DQ + 8 s + 0..7], DQ = dp/4, s < DQ/8.
+// Every loop keeps kPrepU loads in flight per thread: indices are clamped
+// into range so each load is issued unconditionally, and out-of-range values
+// are masked afterwards (a guarded load would wait before the next one).
+constexpr int kPrepU = 8;
+
+// C[j][k] for a padded position (+0 outside K x d), loaded unconditionally
+// and masked bitwise (a select on the loaded value may be turned back into
+// a branch around the load).
+__device__ __forceinline__ float c_at(const AssignParams& p, int64_t j, int64_t k) {
+  const float v = p.C[min(j, (int64_t)p.K - 1) * p.d + min(k, (int64_t)p.d - 1)];
+  const uint32_t keep = (j < p.K && k < p.d) ? 0xFFFFFFFFu : 0u;
+  return __uint_as_float(__float_as_uint(v) & keep);
+}
+
+// out(e, val(e)) for e = tid, tid + stride, ... < total: whole batches of
+// kPrepU elements per thread load everything first and store without a
+// guard (a guarded store lets the compiler sink its load under the guard,
+// one wait per element); the last partial batch goes one element at a time.
+template <typename I, typename V, typename O>
+__device__ __forceinline__ void strided_batched(I tid, I stride, I total, V&& val, O&& out) {
+  const I full = total / (kPrepU * stride) * (kPrepU * stride);
+  for (I e0 = tid; e0 < full; e0 += kPrepU * stride) {
+    decltype(val(e0)) v[kPrepU];
+#pragma unroll
+    for (int u = 0; u < kPrepU; ++u) v[u] = val(e0 + u * stride);
+#pragma unroll
+    for (int u = 0; u < kPrepU; ++u) out(e0 + u * stride, v[u]);
+  }
+  for (I e = full + tid; e < total; e += stride) out(e, val(e));
+}
+
 // A thread takes items tid, tid + stride, ...; it returns the bits of the
 // largest ||c_j||^2 it saw (as unsigned integers non-negative floats order
 // like their values, and NaN above them).
-__device__ uint32_t prep_part(const AssignParams& p, int fmt, int64_t tid, int64_t stride) {
+// I: the index type (32-bit when every index fits, so the divisions below
+// stay short and branch-free).
+template <typename I>
+__device__ uint32_t prep_part(const AssignParams& p, int fmt, I tid, I stride) {
   const int Kt = p.Kp / 16;
   const int DQ = p.dp / 4;
   uint32_t mx = 0u;
-  for (int64_t j = tid; j < p.Kp; j += stride) {
-    float a = 0.0f;
-    if (j < p.K)
-      for (int k = 0; k < p.d; ++k) {
-        const float c = p.C[j * p.d + k];
-        a = fmaf(c, c, a);
-      }
+  for (I j = tid; j < p.Kp; j += stride) {
+    float a = 0.0f;  // sum over k in order
+    for (int k0 = 0; k0 < p.d; k0 += kPrepU) {
+      float c[kPrepU];
+#pragma unroll
+      for (int u = 0; u < kPrepU; ++u) c[u] = c_at(p, j, k0 + u);
+#pragma unroll
+      for (int u = 0; u < kPrepU; ++u) a = fmaf(c[u], c[u], a);  // +0 past d: a unchanged
+    }
     p.cn[j] = j < p.K ? -0.5f * a : -INFINITY;  // exact scaling
     if (j < p.K) mx = max(mx, __float_as_uint(a));
   }
   if (fmt == FMT_F32) {
     float* Cp = (float*)const_cast<void*>(p.Cp);
-    const int64_t total = (int64_t)Kt * DQ * 64;
-    for (int64_t e = tid; e < total; e += stride) {
-      const int lane = (int)(e % 64);
-      const int s = (int)((e / 64) % DQ);
-      const int jt = (int)(e / 64 / DQ);
-      const int j = 16 * jt + lane % 16, k = (lane / 16) * DQ + s;
-      Cp[e] = (j < p.K && k < p.d) ? p.C[(int64_t)j * p.d + k] : 0.0f;
-    }
+    strided_batched(
+        tid, stride, (I)Kt * DQ * 64,
+        [&](I e) {
+          const int lane = (int)(e % 64);
+          const int s = (int)((e / 64) % DQ);
+          const I jt = e / 64 / DQ;
+          return c_at(p, 16 * jt + lane % 16, (lane / 16) * DQ + s);
+        },
+        [&](I e, float v) { Cp[e] = v; });
   } else {
     uint16_t* Cp = (uint16_t*)const_cast<void*>(p.Cp);
     const int S = DQ / 8;
-    const int64_t total = (int64_t)Kt * 2 * S * 64 * 8;
-    for (int64_t e = tid; e < total; e += stride) {
-      const int t = (int)(e % 8);
-      const int lane = (int)((e / 8) % 64);
-      const int s = (int)((e / 512) % S);
-      const int h = (int)((e / 512 / S) % 2);
-      const int jt = (int)(e / 512 / S / 2);
-      const int j = 16 * jt + lane % 16, k = (lane / 16) * DQ + 8 * s + t;
-      const float c = (j < p.K && k < p.d) ? p.C[(int64_t)j * p.d + k] : 0.0f;
-      const uint32_t hb = __float_as_uint(c);
-      const uint32_t hi = ((hb + 0x7FFFu + ((hb >> 16) & 1u)) >> 16) & 0xFFFFu;  // RNE
-      const float rem = c - __uint_as_float(hi << 16);                              // exact
-      const uint32_t rb = __float_as_uint(rem);
-      const uint32_t lo = ((rb + 0x7FFFu + ((rb >> 16) & 1u)) >> 16) & 0xFFFFu;
-      Cp[e] = (uint16_t)(h == 0 ? hi : lo);
-    }
+    strided_batched(
+        tid, stride, (I)Kt * 2 * S * 64 * 8,
+        [&](I e) {
+          const int t = (int)(e % 8);
+          const int lane = (int)((e / 8) % 64);
+          const int s = (int)((e / 512) % S);
+          const I jt = e / 512 / S / 2;
+          return c_at(p, 16 * jt + lane % 16, (lane / 16) * DQ + 8 * s + t);
+        },
+        [&](I e, float c) {
+          const uint32_t hb = __float_as_uint(c);
+          const uint32_t hi = ((hb + 0x7FFFu + ((hb >> 16) & 1u)) >> 16) & 0xFFFFu;  // RNE
+          const float rem = c - __uint_as_float(hi << 16);                              // exact
+          const uint32_t rb = __float_as_uint(rem);
+          const uint32_t lo = ((rb + 0x7FFFu + ((rb >> 16) & 1u)) >> 16) & 0xFFFFu;
+          Cp[e] = (uint16_t)((e / 512 / S) % 2 == 0 ? hi : lo);  // part 0 high, 1 remainder
+        });
   }
   return mx;
 }
 
 __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fmt) {
-  const uint32_t mx = prep_part(p, fmt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+  const uint32_t mx =
+      prep_part<int64_t>(p, fmt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
   if (mx) atomicMax(reinterpret_cast<unsigned int*>(p.cmax2), mx);
 }
 
@@ -477,16 +516,15 @@ void assign_mfma_kernel(AssignParams p) {
 // value serves all kRR rows, whose values are the same for all lanes.
 constexpr int kRR = 8;
 
-__device__ void transpose_part(const AssignParams& p, int64_t tid, int64_t stride) {
-  const int64_t total = (int64_t)p.d * p.Kq;
-  for (int64_t e = tid; e < total; e += stride) {
-    const int64_t k = e / p.Kq, j = e % p.Kq;
-    p.Ct[e] = j < p.K ? p.C[j * p.d + k] : 0.0f;
-  }
+template <typename I>
+__device__ void transpose_part(const AssignParams& p, I tid, I stride) {
+  strided_batched(
+      tid, stride, (I)p.d * p.Kq, [&](I e) { return c_at(p, e % p.Kq, e / p.Kq); },
+      [&](I e, float v) { p.Ct[e] = v; });
 }
 
 __global__ __launch_bounds__(256) void assign_transpose_kernel(AssignParams p) {
-  transpose_part(p, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+  transpose_part<int64_t>(p, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
 }
 
 // A workgroup takes kRR rows at once and its four waves split the centres
@@ -623,8 +661,9 @@ __global__ __launch_bounds__(1024) void assign_setup_kernel(AssignParams p, int 
     p.ctl->status = KMPP_OK;
     p.ctl->nflag = 0u;
   }
-  transpose_part(p, tid, 1024);
-  uint32_t mx = prep_part(p, fmt, tid, 1024);
+  // every index fits 32 bits here (Kp * dp <= 65536, d <= 256)
+  transpose_part<uint32_t>(p, (uint32_t)tid, 1024u);
+  uint32_t mx = prep_part<uint32_t>(p, fmt, (uint32_t)tid, 1024u);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
   if (lane == 0) smx[wave] = mx;
