@@ -57,6 +57,26 @@ def test_f32_shapes(kl, d, K):
     check_assign(Xh.numpy(), Ch.numpy(), lab, mind)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("K", [1024, 1025])
+def test_centre_setup_paths(kl, dtype, K):
+    # d = 64 pads to 64 columns in both formats: K = 1024 is a centre block of
+    # exactly 65,536 padded elements (prepared by one workgroup), K = 1025
+    # pads to 1040 rows (the three-kernel setup)
+    N, d = 3_001, 64
+    Xh = kmpp_synth.gaussian(N, d, seed=K + 7 * dtype, scale=2.0)
+    Ch = Xh[torch.randperm(N, generator=torch.Generator().manual_seed(K))[:K]].contiguous()
+    print("assign setup path", dtype, N, d, K, flush=True)
+    if dtype == 0:
+        lab, mind = run_assign(kl, Xh.cuda(), Ch.cuda())
+        Xd = Xh.numpy()
+    else:
+        q, _ = kl.kmpp_quantize(Xh.cuda(), kl.KMPP_BF16)
+        lab, mind = run_assign(kl, q, Ch.cuda(), dtype=kl.KMPP_BF16)
+        Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
+    check_assign(Xd, Ch.numpy(), lab, mind)
+
+
 def test_exact_ties_go_to_smallest_index(kl):
     # integer lattice with duplicated centres: exact ties everywhere
     Xh = kmpp_synth.lattice(20_000, 4, lim=5, seed=1)
