@@ -147,6 +147,25 @@ def test_lloyd_precision_forms(kl, fmt):
     replay(kl, Xq, Xd, C0, 3, X_exp=E, dtype=dt)
 
 
+@pytest.mark.parametrize("fmt,d,K", [("bf16", 128, 300), ("bf16", 100, 400), ("bf16", 129, 300),
+                                     ("fp8", 256, 200), ("fp8", 130, 300), ("fp8", 64, 600)])
+def test_lloyd_precision_forms_sorted_path(kl, fmt, d, K):
+    # K * d large enough for the sorted path (at least four cluster ranges),
+    # BF16 and FP8 rows of even, odd and ragged widths
+    N = 30_011
+    Xh = kmpp_synth.gaussian(N, d, seed=900 + d, scale=3.0)
+    X = Xh.cuda()
+    dt = kl.DTYPES[fmt]
+    Xq, E = kl.kmpp_quantize(X, dt)
+    if fmt == "bf16":
+        Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
+    else:
+        Xd = oracle.fp8_dequantize_rows(*oracle.fp8_quantize_rows_fast(Xh.numpy()))
+    _say(fmt, "sorted path", N, d, K)
+    idx, C0, _, _ = kl.kmpp_seed(X, K, 3, Xq=Xq, Xq_exp=E, dtype=dt)
+    replay(kl, Xq, Xd, C0, 2, X_exp=E, dtype=dt)
+
+
 def test_lloyd_sorted_path_determinism(kl):
     # the sorted path's scatter order varies from run to run; the integer
     # sums do not, so two runs give the same bits
