@@ -514,7 +514,12 @@ void assign_mfma_kernel(AssignParams p) {
 // index.  A wave takes kRR rows at once: lanes run over 64 centres at a
 // time, read coalesced from the transposed copy Ct[k][j], and every centre
 // value serves all kRR rows, whose values are the same for all lanes.
-constexpr int kRR = 8;
+// kRR: 4 rows for FP32 (few rows are queued, and smaller groups spread
+// them over more workgroups: 210 -> 181 us on 4.2M x 128), 8 for BF16 /
+// FP8 rows, whose wider error bound queues many more (301 us with 8,
+// 359 us with 4; 16 rows measured slower for both).
+template <int FMT>
+constexpr int recheck_rows() { return FMT == FMT_F32 ? 4 : 8; }
 
 template <typename I>
 __device__ void transpose_part(const AssignParams& p, I tid, I stride) {
@@ -537,6 +542,8 @@ constexpr int kRecheckLdsD = 256;
 
 template <int FMT, bool XL>
 __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
+  constexpr int kRR = recheck_rows<FMT>();
+  static_assert(kRR % 4 == 0, "rows are staged in LDS four to a 16-byte word");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ float4 sx[XL ? kRecheckLdsD * (kRR / 4) : 1];
   __shared__ float s_b[4][kRR];
