@@ -131,6 +131,9 @@ typedef struct kmpp_seed_opts {
   int32_t centre_source;/* where the passes take the current centre from: 0 (default: LDS),
                            KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR or KMPP_CENTRE_GLOBAL */
   int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS or KMPP_DRAW_KERNEL */
+  double* out_sumD;     /* device FP64 [K] or NULL: [m] (m >= 1) = the sum of D that draw m
+                           inverted (the denominator of P(n_l) in Algorithm 1, summed in
+                           FP64 in the fixed tile order); [0] = 0 */
 } kmpp_seed_opts;
 
 /*

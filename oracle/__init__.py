@@ -69,6 +69,12 @@ def lib():
         L.kmo_upper_bound.restype = i64
         L.kmo_seed.argtypes = [P, P, i64, i32, i32, u64, u32, i32, P, P, P, P, i32]
         L.kmo_seed.restype = ctypes.c_int
+        L.kmo_seed_range.argtypes = [P, P, i64, i32, i32, u64, u32, i32, P, i32, i32, P, P, P, i32]
+        L.kmo_seed_range.restype = ctypes.c_int
+        L.kmo_draw.argtypes = [P, i64, ctypes.c_double, P, P, i32]
+        L.kmo_draw.restype = ctypes.c_int
+        L.kmo_wdraw.argtypes = [P, i64, ctypes.c_double, P, P]
+        L.kmo_wdraw.restype = ctypes.c_int
         L.kmo_assign.argtypes = [P, i64, i32, P, i32, P, P, P, i32]
         L.kmo_assign.restype = ctypes.c_int
         L.kmo_assign_rows.argtypes = [P, i32, P, i64, P, i32, P, P, P]
@@ -141,11 +147,12 @@ class SeedResult:
 
 
 def seed(X, K: int, seed: int = 0, inst: int = 0, Xc=None, zero_seed_rows: bool = False,
-         replay=None, nthreads: int = 0) -> SeedResult:
+         replay=None, nthreads: int = 0, chunk: int = 0, progress=None) -> SeedResult:
     """k-means++ seeding in FP64 (Algorithm 1).  ``X`` holds the values
     distances use; ``Xc`` (default ``X``) the values centres take.  With
     ``replay`` (the GPU's indices) each step is checked on the D built from
-    the replayed seeds."""
+    the replayed seeds.  ``chunk`` > 0 runs the passes in ranges of that many
+    (the same arithmetic) and calls ``progress(m)`` after each range."""
     Xd = _f32(X)
     N, d = Xd.shape
     Xc_ = Xd if Xc is None else _f32(Xc)
@@ -157,11 +164,49 @@ def seed(X, K: int, seed: int = 0, inst: int = 0, Xc=None, zero_seed_rows: bool 
     if replay is not None:
         rp = np.ascontiguousarray(np.asarray(replay, dtype=np.int64))
         assert rp.size == K
-    st = lib().kmo_seed(_ptr(Xd), _ptr(Xc_), N, d, K, seed, inst, int(zero_seed_rows),
-                        _ptr(rp), _ptr(idx), _ptr(D), _ptr(rec), nthreads)
+    if chunk <= 0:
+        st = lib().kmo_seed(_ptr(Xd), _ptr(Xc_), N, d, K, seed, inst, int(zero_seed_rows),
+                            _ptr(rp), _ptr(idx), _ptr(D), _ptr(rec), nthreads)
+    else:
+        st = OK
+        for m0 in range(1, K + 1, chunk):
+            m1 = min(K, m0 + chunk - 1)
+            s1 = lib().kmo_seed_range(_ptr(Xd), _ptr(Xc_), N, d, K, seed, inst, int(zero_seed_rows), _ptr(rp),
+                                      m0, m1, _ptr(idx), _ptr(D), _ptr(rec), nthreads)
+            if s1 < 0:
+                st = s1
+                break
+            if s1 == W_DEGENERATE:
+                st = W_DEGENERATE
+            if progress is not None:
+                progress(m1)
     if st == E_INVALID:
         raise ValueError("oracle: invalid arguments")
     return SeedResult(idx, D, rec, st)
+
+
+def draw(D, u: float, nthreads: int = 0):
+    """One inverse-CDF draw of Algorithm 1 on a given D with a given u:
+    returns (index or -1, status, rec4 = (T, t, S_{i-1}, S_i))."""
+    D = np.ascontiguousarray(np.asarray(D, dtype=np.float64))
+    out = np.zeros(1, dtype=np.int64)
+    rec = np.zeros(4, dtype=np.float64)
+    st = lib().kmo_draw(_ptr(D), D.size, float(u), _ptr(out), _ptr(rec), nthreads)
+    if st == E_INVALID:
+        raise ValueError("oracle: invalid arguments")
+    return int(out[0]), st, rec
+
+
+def wdraw(share, u: float):
+    """One draw of the weighted k-means|| recluster on given shares (w or
+    w * D) with a given u: returns (index or -1, status, rec4)."""
+    sh = np.ascontiguousarray(np.asarray(share, dtype=np.float64))
+    out = np.zeros(1, dtype=np.int64)
+    rec = np.zeros(4, dtype=np.float64)
+    st = lib().kmo_wdraw(_ptr(sh), sh.size, float(u), _ptr(out), _ptr(rec))
+    if st == E_INVALID:
+        raise ValueError("oracle: invalid arguments")
+    return int(out[0]), st, rec
 
 
 def assign(X, C, nthreads: int = 0):

@@ -156,7 +156,73 @@ static int64_t kmo_uniform_index(double u, int64_t N) {
 }
 
 /*
- * k-means++ seeding, Algorithm 1 with the readings above.
+ * One draw of Algorithm 1 (the P(n_l) line with the readings above) on the
+ * current D: S = inclusive FP64 prefix of D in index order (fixed chunks),
+ * T = S_{N-1}, t = u * T (one IEEE multiply), i = min { i : S_i > t }; if
+ * no such i exists (t >= S_{N-1}), the last i with D_i > 0.  T == 0: the
+ * uniform index and KMO_W_DEGENERATE; T not finite: KMO_E_NONFINITE (no
+ * index).  *T_out, *t_out receive T and t.
+ */
+static int kmo_draw_on(const double* D, double* S, double* chunk, int64_t N, double u, int nt, int64_t* out_i,
+                       double* T_out, double* t_out) {
+  const double T = kmo_prefix(D, S, chunk, N, nt);
+  volatile double tv = u * T; /* one IEEE multiply */
+  const double t = tv;
+  *T_out = T;
+  *t_out = t;
+  if (!isfinite(T)) return KMO_E_NONFINITE;
+  if (T == 0.0) {
+    *out_i = kmo_uniform_index(u, N);
+    return KMO_W_DEGENERATE;
+  }
+  int64_t i = kmo_upper_bound(S, N, t);
+  if (i >= N) { /* t >= S_{N-1}: the last positive D */
+    i = N - 1;
+    while (i > 0 && !(D[i] > 0.0)) --i;
+  }
+  *out_i = i;
+  return KMO_OK;
+}
+
+/*
+ * The draw alone, with u given: for checking the inverse-CDF rule, its
+ * boundaries and its fallbacks directly.  rec4 (nullable): T, t, S_{i-1},
+ * S_i (S_{i-1} = 0 for i = 0; NaN where there is no index).  Returns
+ * KMO_OK, KMO_W_DEGENERATE, KMO_E_NONFINITE or KMO_E_INVALID.
+ */
+int kmo_draw(const double* D, int64_t N, double u, int64_t* out_i, double* rec4, int32_t nthreads) {
+  if (!D || !out_i || N < 1) return KMO_E_INVALID;
+  const int nt = kmo_threads(nthreads);
+  double* S = (double*)malloc(sizeof(double) * (size_t)N);
+  double* chunk = (double*)malloc(sizeof(double) * (size_t)((N + KMO_CHUNK - 1) / KMO_CHUNK));
+  if (!S || !chunk) {
+    free(S);
+    free(chunk);
+    return KMO_E_INVALID;
+  }
+  double T, t;
+  int64_t i = -1;
+  const int st = kmo_draw_on(D, S, chunk, N, u, nt, &i, &T, &t);
+  *out_i = i;
+  if (rec4) {
+    rec4[0] = T;
+    rec4[1] = t;
+    rec4[2] = (i > 0 && i < N) ? S[i - 1] : (i == 0 ? 0.0 : NAN);
+    rec4[3] = (i >= 0 && i < N) ? S[i] : NAN;
+  }
+  free(S);
+  free(chunk);
+  return st;
+}
+
+/*
+ * k-means++ seeding, Algorithm 1 with the readings above, passes
+ * m_begin..m_end (1 <= m_begin <= m_end <= K) of a run: pass m moves every
+ * D to its distance to seed m-1 if that is smaller (pass 1 replaces the
+ * initial +infinity), and for m < K draws seed m.  D must hold the state
+ * after pass m_begin - 1 (anything for m_begin = 1) and out_idx[0..m_begin-1]
+ * the earlier seeds (the first seed is drawn here when m_begin = 1).  A run
+ * split into consecutive ranges computes exactly what one range computes.
  *
  * Xd     [N*d] values distances are computed from (FP32 data or dequantised rows)
  * Xc     [N*d] values the centres take (FP32 data); may equal Xd
@@ -165,16 +231,18 @@ static int64_t kmo_uniform_index(double u, int64_t N) {
  *        (the GPU's index), while out_idx[m] is still the oracle's own
  *        draw from the same D; this checks each draw independently.
  * out_idx [K]   the oracle's draws
- * out_D   [N]   final nearest squared distance (FP64)
+ * D       [N]   nearest squared distance (FP64), in and out
  * rec     [K*8] or NULL, per step m >= 1:
  *        T, t, S_{i-1}, S_i (oracle's own i), S_{g-1}, S_g, D_g (g = replay[m],
  *        or the oracle's own index without replay), u
- * Returns 0, KMO_W_DEGENERATE, or a negative error.
+ * Returns 0, KMO_W_DEGENERATE (some draw in the range was degenerate), or a
+ * negative error.
  */
-int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, uint64_t seed,
-             uint32_t inst, int32_t zero_seed_rows, const int64_t* replay, int64_t* out_idx,
-             double* out_D, double* rec, int32_t nthreads) {
-  if (!Xd || !Xc || !out_idx || !out_D || N < 1 || d < 1 || K < 1 || K > N) return KMO_E_INVALID;
+int kmo_seed_range(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, uint64_t seed,
+                   uint32_t inst, int32_t zero_seed_rows, const int64_t* replay, int32_t m_begin, int32_t m_end,
+                   int64_t* out_idx, double* D, double* rec, int32_t nthreads) {
+  if (!Xd || !Xc || !out_idx || !D || N < 1 || d < 1 || K < 1 || K > N) return KMO_E_INVALID;
+  if (m_begin < 1 || m_end < m_begin || m_end > K) return KMO_E_INVALID;
   const int nt = kmo_threads(nthreads);
   const int64_t nch = (N + KMO_CHUNK - 1) / KMO_CHUNK;
   double* S = (double*)malloc(sizeof(double) * (size_t)N);
@@ -187,13 +255,12 @@ int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, 
     return KMO_E_INVALID;
   }
   int status = KMO_OK;
-  double* D = out_D;
 
-  const double u0 = kmo_uniform(seed, 0u, inst);
-  out_idx[0] = kmo_uniform_index(u0, N);
-  int64_t prev = replay ? replay[0] : out_idx[0];
+  if (m_begin == 1) out_idx[0] = kmo_uniform_index(kmo_uniform(seed, 0u, inst), N);
+  int64_t prev = replay ? replay[m_begin - 1] : out_idx[m_begin - 1];
+  if (prev < 0 || prev >= N) status = KMO_E_INVALID;
 
-  for (int32_t m = 1; m <= K; ++m) {
+  for (int32_t m = m_begin; m <= m_end && status >= 0; ++m) {
     /* centre c_{m-1}: the original row of the previous seed */
     for (int32_t j = 0; j < d; ++j) c[j] = (double)Xc[prev * (int64_t)d + j];
     /* D_i = min(D_i, ||x_i - c||^2); the first pass replaces +inf */
@@ -205,24 +272,15 @@ int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, 
     if (zero_seed_rows) D[prev] = 0.0;
     if (m == K) break;
 
-    const double T = kmo_prefix(D, S, chunk, N, nt);
     const double u = kmo_uniform(seed, (uint32_t)m, inst);
-    volatile double tv = u * T; /* one IEEE multiply */
-    const double t = tv;
-    int64_t i;
-    if (!isfinite(T)) {
-      status = KMO_E_NONFINITE;
+    double T, t;
+    int64_t i = -1;
+    const int st = kmo_draw_on(D, S, chunk, N, u, nt, &i, &T, &t);
+    if (st < 0) {
+      status = st;
       break;
-    } else if (T == 0.0) {
-      i = kmo_uniform_index(u, N);
-      status = KMO_W_DEGENERATE;
-    } else {
-      i = kmo_upper_bound(S, N, t);
-      if (i >= N) { /* t >= S_{N-1} through rounding: last positive D */
-        i = N - 1;
-        while (i > 0 && !(D[i] > 0.0)) --i;
-      }
     }
+    if (st == KMO_W_DEGENERATE) status = KMO_W_DEGENERATE;
     out_idx[m] = i;
     const int64_t g = replay ? replay[m] : i;
     if (rec) {
@@ -246,6 +304,13 @@ int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, 
   free(chunk);
   free(c);
   return status;
+}
+
+/* The whole run (passes 1..K); out_D receives the final D. */
+int kmo_seed(const float* Xd, const float* Xc, int64_t N, int32_t d, int32_t K, uint64_t seed,
+             uint32_t inst, int32_t zero_seed_rows, const int64_t* replay, int64_t* out_idx,
+             double* out_D, double* rec, int32_t nthreads) {
+  return kmo_seed_range(Xd, Xc, N, d, K, seed, inst, zero_seed_rows, replay, 1, K, out_idx, out_D, rec, nthreads);
 }
 
 /* Nearest-seed assignment (output O of Algorithm 1): label = smallest j
@@ -592,6 +657,58 @@ double kmo_uniform4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32
 }
 
 /*
+ * One draw of the weighted recluster (step 4 of k-means||): S = inclusive
+ * FP64 prefix of the shares in order (sequential), T = S_{n-1},
+ * t = u * T (one IEEE multiply), the first j with S_j > t; if none (t >= T),
+ * the last j whose share raised S.  T == 0: the uniform index and
+ * KMO_W_DEGENERATE; T not finite: KMO_E_NONFINITE (no index).
+ */
+static int kmo_wdraw_on(const double* share, double* S, int64_t n, double u, int64_t* out_j, double* T_out,
+                        double* t_out) {
+  double acc = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    acc += share[j];
+    S[j] = acc;
+  }
+  const double T = acc;
+  volatile double tv = u * T;
+  const double t = tv;
+  *T_out = T;
+  *t_out = t;
+  if (!isfinite(T)) return KMO_E_NONFINITE;
+  if (T == 0.0) {
+    *out_j = kmo_uniform_index(u, n);
+    return KMO_W_DEGENERATE;
+  }
+  int64_t g = kmo_upper_bound(S, n, t);
+  if (g >= n) {
+    g = n - 1;
+    while (g > 0 && S[g] == S[g - 1]) --g;
+  }
+  *out_j = g;
+  return KMO_OK;
+}
+
+/* The recluster draw alone, with u given (rec4 as for kmo_draw). */
+int kmo_wdraw(const double* share, int64_t n, double u, int64_t* out_j, double* rec4) {
+  if (!share || !out_j || n < 1) return KMO_E_INVALID;
+  double* S = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!S) return KMO_E_INVALID;
+  double T, t;
+  int64_t g = -1;
+  const int st = kmo_wdraw_on(share, S, n, u, &g, &T, &t);
+  *out_j = g;
+  if (rec4) {
+    rec4[0] = T;
+    rec4[1] = t;
+    rec4[2] = (g > 0 && g < n) ? S[g - 1] : (g == 0 ? 0.0 : NAN);
+    rec4[3] = (g >= 0 && g < n) ? S[g] : NAN;
+  }
+  free(S);
+  return st;
+}
+
+/*
  * X [N*d] FP32 points; K centres; cap = capacity of the candidate list.
  * Outputs: cand [cap] candidate point indices, *ncand, round_end [rounds+1]
  * (candidates after the first point and after each round), weights [cap],
@@ -692,35 +809,21 @@ int kmo_kmpar(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, ui
   /* 4. weighted k-means++ over the candidates */
   double* Dc = (double*)malloc(sizeof(double) * (size_t)mc);
   double* S = (double*)malloc(sizeof(double) * (size_t)mc);
+  double* Sh = (double*)malloc(sizeof(double) * (size_t)mc);
   for (int64_t j = 0; j < mc; ++j) Dc[j] = INFINITY;
   for (int32_t k = 0; k < K; ++k) {
     /* weights of this draw: w (first) or w * Dc */
-    double acc = 0.0;
-    for (int64_t j = 0; j < mc; ++j) {
-      const double v = k == 0 ? (double)W[j] : (double)W[j] * Dc[j];
-      acc += v;
-      S[j] = acc;
-    }
-    const double T = acc;
+    for (int64_t j = 0; j < mc; ++j) Sh[j] = k == 0 ? (double)W[j] : (double)W[j] * Dc[j];
     const double u = kmo_u_ctr(seed, (uint32_t)k, inst, 0u, 2u);
-    int64_t g;
+    int64_t g = -1;
+    double T, t;
     double* rr = rec ? rec + (int64_t)k * 8 : NULL;
-    if (!isfinite(T)) {
-      status = KMO_E_NONFINITE;
+    const int st = kmo_wdraw_on(Sh, S, mc, u, &g, &T, &t);
+    if (st < 0) {
+      status = st;
       break;
     }
-    volatile double tv = u * T;
-    const double t = tv;
-    if (T == 0.0) {
-      g = kmo_uniform_index(u, mc);
-      if (status == KMO_OK) status = KMO_W_DEGENERATE;
-    } else {
-      g = kmo_upper_bound(S, mc, t);
-      if (g >= mc) {
-        g = mc - 1;
-        while (g > 0 && S[g] == (g > 0 ? S[g - 1] : 0.0)) --g;
-      }
-    }
+    if (st == KMO_W_DEGENERATE && status == KMO_OK) status = KMO_W_DEGENERATE;
     out_idx[k] = C[g];
     const int64_t gr = rp_idx ? -1 : g; /* replayed candidate position, found below */
     int64_t gp = gr;
@@ -752,6 +855,7 @@ int kmo_kmpar(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, ui
   }
   free(Dc);
   free(S);
+  free(Sh);
   free(D);
   free(lab);
   free(c);

@@ -51,7 +51,7 @@ class SeedOpts(ctypes.Structure):
     _fields_ = [("instance", ctypes.c_uint32), ("threads", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
                 ("loads_per_lane", ctypes.c_int16), ("row_loads", ctypes.c_int16),
                 ("out_recheck", ctypes.c_void_p), ("step_events", ctypes.c_void_p),
-                ("centre_source", ctypes.c_int32), ("draw", ctypes.c_int32)]
+                ("centre_source", ctypes.c_int32), ("draw", ctypes.c_int32), ("out_sumD", ctypes.c_void_p)]
 
 
 class Instance(ctypes.Structure):
@@ -150,6 +150,61 @@ def _require_cuda(*ts):
             raise ValueError("libkmpp takes contiguous CUDA (HIP) tensors")
 
 
+# The C ABI takes bare pointers and cannot see a buffer's size or element
+# type, so every tensor is checked here before its pointer is passed: a
+# wrong dtype or a short buffer would make the kernels read or write past
+# the allocation.
+_ELEM_BYTES = {KMPP_F32: 4, KMPP_BF16: 2, KMPP_FP8_E4M3: 1}
+
+
+def _expect(t, name, *, dtype=None, itemsize=None, shape=None, numel=None, min_numel=None, required=True):
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if itemsize is not None and t.element_size() != itemsize:
+        raise ValueError(f"{name} must have {itemsize}-byte elements, got {t.element_size()} ({t.dtype})")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} must hold at least {min_numel} elements, got {t.numel()}")
+
+
+def _rows(X, name="X"):
+    if X is None or X.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D [N, d] tensor")
+    return int(X.shape[0]), int(X.shape[1])
+
+
+def _check_dtype(dtype):
+    if dtype not in _ELEM_BYTES:
+        raise ValueError(f"dtype must be KMPP_F32, KMPP_BF16 or KMPP_FP8_E4M3, got {dtype}")
+
+
+def _check_rows(X, X_exp, dtype, name="X"):
+    """Rows stored in `dtype` (FP32, BF16 or FP8 with int8 row exponents)."""
+    _check_dtype(dtype)
+    N, d = _rows(X, name)
+    _expect(X, name, itemsize=_ELEM_BYTES[dtype])
+    if dtype == KMPP_F32:
+        _expect(X, name, dtype=torch.float32)
+    if dtype == KMPP_FP8_E4M3:
+        _expect(X_exp, f"{name}_exp", dtype=torch.int8, numel=N)
+    return N, d
+
+
+def _centres(C, d):
+    """FP32 [K, d] centres for rows of width d; returns K."""
+    if C is None or C.dim() != 2 or int(C.shape[1]) != d:
+        raise ValueError(f"C must be a 2-D [K, {d}] tensor")
+    _expect(C, "C", dtype=torch.float32)
+    return int(C.shape[0])
+
+
 def workspace(nbytes: int, device) -> torch.Tensor:
     ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
     off = (-ws.data_ptr()) % 256
@@ -164,23 +219,37 @@ def kmpp_seed_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -> 
 def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D=None, out_idx=None, Xq=None,
               Xq_exp=None, dtype: int = KMPP_F32, instance: int = 0, threads: int = 0, rows_per_tile: int = 0,
               loads_per_lane: int = 0, row_loads: int = -1, centre_source: int = 0, out_recheck=None,
-              step_events=None, draw: int = KMPP_DRAW_AUTO, ws=None, stream=None):
+              out_sumD=None, step_events=None, draw: int = KMPP_DRAW_AUTO, ws=None, stream=None):
     """k-means++ seeding of the rows of X (FP32 [N, d]).  Returns
     (idx int64 [K], centers FP32 [K, d], D FP32 [N], workspace).
     ``row_loads`` (KMPP_ROWS_*) and ``centre_source`` (KMPP_CENTRE_*) pick
     the memory spaces of the passes (-1 / 0: tuned default); ``draw``
-    (KMPP_DRAW_*) runs each draw in an extra workgroup of the pass launch or
-    in a kernel of its own."""
-    _require_cuda(X, Xq, Xq_exp)
-    N, d = X.shape
+    (KMPP_DRAW_*) runs each draw at the start of the next pass or in a
+    kernel of its own; ``out_recheck`` (FP32 [2K]) and ``out_sumD`` (FP64
+    [K]) receive the per-draw diagnostics described in kmpp.h."""
+    N, d = _rows(X)
+    _expect(X, "X", dtype=torch.float32)
+    _check_dtype(dtype)
+    if dtype != KMPP_F32:
+        _expect(Xq, "Xq", itemsize=_ELEM_BYTES[dtype])
+        _expect(Xq, "Xq", shape=(N, d))
+        if dtype == KMPP_FP8_E4M3:
+            _expect(Xq_exp, "Xq_exp", dtype=torch.int8, numel=N)
     dev = X.device
     out_centers = torch.empty((K, d), dtype=torch.float32, device=dev) if out_centers is None else out_centers
     out_D = torch.empty(N, dtype=torch.float32, device=dev) if out_D is None else out_D
     out_idx = torch.empty(K, dtype=torch.int64, device=dev) if out_idx is None else out_idx
+    _expect(out_centers, "out_centers", dtype=torch.float32, numel=K * d)
+    _expect(out_D, "out_D", dtype=torch.float32, numel=N)
+    _expect(out_idx, "out_idx", dtype=torch.int64, numel=K)
+    _expect(out_recheck, "out_recheck", dtype=torch.float32, min_numel=2 * K, required=False)
+    _expect(out_sumD, "out_sumD", dtype=torch.float64, min_numel=K, required=False)
+    _require_cuda(X, Xq, Xq_exp, out_centers, out_D, out_idx, out_recheck, out_sumD, ws)
     if ws is None:
         ws = workspace(kmpp_seed_workspace_bytes(N, d, K, dtype), dev)
     opts = SeedOpts(instance, threads, rows_per_tile, loads_per_lane, row_loads,
-                    None if out_recheck is None else out_recheck.data_ptr(), step_events, centre_source, draw)
+                    None if out_recheck is None else out_recheck.data_ptr(), step_events, centre_source, draw,
+                    None if out_sumD is None else out_sumD.data_ptr())
     rc = lib().kmpp_seed(_ptr(X), N, d, K, seed, _ptr(out_centers), _ptr(out_D), _ptr(out_idx), _ptr(Xq),
                          _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "kmpp_seed")
@@ -197,8 +266,11 @@ def kmpp_status(ws: torch.Tensor, stream=None) -> int:
 def kmpp_quantize(X: torch.Tensor, dtype: int, stream=None):
     """Returns (Xq, Xq_exp): torch.bfloat16 [N, d] (exp None) or torch.float8_e4m3fn
     [N, d] with int8 [N] row exponents."""
+    N, d = _rows(X)
+    _expect(X, "X", dtype=torch.float32)
+    if dtype not in (KMPP_BF16, KMPP_FP8_E4M3):
+        raise ValueError("kmpp_quantize stores KMPP_BF16 or KMPP_FP8_E4M3 rows")
     _require_cuda(X)
-    N, d = X.shape
     if dtype == KMPP_BF16:
         Xq = torch.empty((N, d), dtype=torch.bfloat16, device=X.device)
         E = None
@@ -218,12 +290,14 @@ def kmpp_assign(X: torch.Tensor, C: torch.Tensor, *, X_exp=None, dtype: int = KM
                 out_mind=None, ws=None, stream=None):
     """Nearest seed of every row.  X is [N, d] in `dtype` (FP32, BF16 as
     uint16, FP8 as uint8 with X_exp).  Returns (labels int32 [N], mind FP32 [N], ws)."""
-    _require_cuda(X, C, X_exp)
-    N, d = X.shape
-    K = C.shape[0]
+    N, d = _check_rows(X, X_exp, dtype)
+    K = _centres(C, d)
     dev = X.device
     out_labels = torch.empty(N, dtype=torch.int32, device=dev) if out_labels is None else out_labels
     out_mind = torch.empty(N, dtype=torch.float32, device=dev) if out_mind is None else out_mind
+    _expect(out_labels, "out_labels", dtype=torch.int32, numel=N)
+    _expect(out_mind, "out_mind", dtype=torch.float32, numel=N)
+    _require_cuda(X, C, X_exp, out_labels, out_mind, ws)
     if ws is None:
         ws = workspace(kmpp_assign_workspace_bytes(N, d, K, dtype), dev)
     rc = lib().kmpp_assign(_ptr(X), _ptr(X_exp), dtype, _ptr(C), N, d, K, _ptr(out_labels), _ptr(out_mind),
@@ -238,12 +312,14 @@ def kmpp_seed_parallel(X: torch.Tensor, K: int, seed: int = 0, *, rounds: int = 
     """k-means|| seeding of the rows of X (FP32 [N, d], d <= 128).  Returns
     (idx int64 [K], centers FP32 [K, d], cand int64 [cap], round_end int32
     [rounds+1], weights int32 [cap], labels int32 [N], ws)."""
-    _require_cuda(X)
-    N, d = X.shape
+    N, d = _rows(X)
+    _expect(X, "X", dtype=torch.float32)
     ell = float(2 * K) if ell is None else float(ell)
     dev = X.device
     cap = int(lib().kmpp_seed_parallel_capacity(N, rounds, ell))
     out_centers = torch.empty((K, d), dtype=torch.float32, device=dev) if out_centers is None else out_centers
+    _expect(out_centers, "out_centers", dtype=torch.float32, numel=K * d)
+    _require_cuda(X, out_centers, ws)
     idx = torch.empty(K, dtype=torch.int64, device=dev)
     cand = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
     rend = torch.empty(rounds + 1, dtype=torch.int32, device=dev)
@@ -271,14 +347,18 @@ def kmpp_lloyd(X: torch.Tensor, C: torch.Tensor, iters: int, *, X_exp=None, dtyp
     """`iters` Lloyd iterations from the centres C (FP32 [K, d], updated in
     place).  X is [N, d] in `dtype`.  Returns (C, labels int32 [N],
     cost FP64 [iters], changed int64 [iters], counts int32 [K], ws)."""
-    _require_cuda(X, C, X_exp)
-    N, d = X.shape
-    K = C.shape[0]
+    N, d = _check_rows(X, X_exp, dtype)
+    K = _centres(C, d)
     dev = X.device
     out_labels = torch.empty(N, dtype=torch.int32, device=dev) if out_labels is None else out_labels
     out_cost = torch.empty(max(iters, 1), dtype=torch.float64, device=dev) if out_cost is None else out_cost
     out_changed = torch.empty(max(iters, 1), dtype=torch.int64, device=dev) if out_changed is None else out_changed
     out_counts = torch.empty(K, dtype=torch.int32, device=dev) if out_counts is None else out_counts
+    _expect(out_labels, "out_labels", dtype=torch.int32, numel=N)
+    _expect(out_cost, "out_cost", dtype=torch.float64, min_numel=iters)
+    _expect(out_changed, "out_changed", dtype=torch.int64, min_numel=iters)
+    _expect(out_counts, "out_counts", dtype=torch.int32, numel=K)
+    _require_cuda(X, C, X_exp, out_labels, out_cost, out_changed, out_counts, ws)
     if ws is None:
         ws = workspace(kmpp_lloyd_workspace_bytes(N, d, K, dtype), dev)
     rc = lib().kmpp_lloyd(_ptr(X), _ptr(X_exp), dtype, N, d, K, _ptr(C), iters, _ptr(out_labels), _ptr(out_cost),
@@ -289,27 +369,38 @@ def kmpp_lloyd(X: torch.Tensor, C: torch.Tensor, iters: int, *, X_exp=None, dtyp
 
 # ---------------------------------------------------------------- batched
 def _instances(Xs, Ks, outs):
+    if len(Xs) != len(Ks) or len(Xs) != len(outs):
+        raise ValueError("one K and one output triple per instance")
     arr = (Instance * len(Xs))()
     for b, (X, K, (C, D, I)) in enumerate(zip(Xs, Ks, outs)):
-        arr[b] = Instance(X.data_ptr(), X.shape[0], X.shape[1], K, C.data_ptr(),
+        N, d = _rows(X, f"Xs[{b}]")
+        _expect(X, f"Xs[{b}]", dtype=torch.float32)
+        _expect(C, f"outs[{b}][0]", dtype=torch.float32, numel=K * d, required=False)
+        _expect(D, f"outs[{b}][1]", dtype=torch.float32, numel=N, required=False)
+        _expect(I, f"outs[{b}][2]", dtype=torch.int64, numel=K, required=False)
+        arr[b] = Instance(X.data_ptr(), X.shape[0], X.shape[1], K, None if C is None else C.data_ptr(),
                           None if D is None else D.data_ptr(), None if I is None else I.data_ptr())
     return arr
 
 
 def kmpp_batched_workspace_bytes(Xs, Ks) -> int:
-    outs = [(X, None, None) for X in Xs]  # pointers are not read for sizing
+    outs = [(None, None, None) for _ in Xs]  # output pointers are not read for sizing
     return int(lib().kmpp_batched_workspace_bytes(_instances(Xs, Ks, outs), len(Xs)))
 
 
 def kmpp_seed_batched_prepare(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stream=None):
     """Plan and upload a batch.  Returns (outs, ws) with outs[b] = (centers, D, idx)."""
-    _require_cuda(*Xs)
+    if len(Xs) < 1:
+        raise ValueError("at least one instance")
     dev = Xs[0].device
     if outs is None:
         outs = [(torch.empty((K, X.shape[1]), dtype=torch.float32, device=dev),
                  torch.empty(X.shape[0], dtype=torch.float32, device=dev),
                  torch.empty(K, dtype=torch.int64, device=dev)) for X, K in zip(Xs, Ks)]
     arr = _instances(Xs, Ks, outs)
+    _require_cuda(*Xs)
+    for o in outs:
+        _require_cuda(*o)
     if ws is None:
         ws = workspace(lib().kmpp_batched_workspace_bytes(arr, len(Xs)), dev)
     _check(lib().kmpp_seed_batched_prepare(arr, len(Xs), seed, _ptr(ws), ws.numel(), _stream(stream)),
@@ -367,8 +458,9 @@ def kmpp_version() -> int:
 def kmpp_read_probe(buf: torch.Tensor, blocks: int = 4096, nontemporal: bool = False, out=None, stream=None):
     """Read-bandwidth probe (measurement helper): reads every byte of `buf`
     once and returns the FP32 per-workgroup sums [blocks]."""
-    _require_cuda(buf)
     out = torch.empty(blocks, dtype=torch.float32, device=buf.device) if out is None else out
+    _expect(out, "out", dtype=torch.float32, min_numel=blocks)
+    _require_cuda(buf, out)
     _check(lib().kmpp_read_probe(_ptr(buf), buf.numel() * buf.element_size(), blocks, int(nontemporal), _ptr(out),
                                  _stream(stream)), "kmpp_read_probe")
     return out

@@ -16,7 +16,6 @@
 namespace kmpp {
 namespace {
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 int elem_bytes(int dtype) { return dtype == KMPP_F32 ? 4 : dtype == KMPP_BF16 ? 2 : 1; }
@@ -47,28 +46,6 @@ constexpr int kFewTiles = 256;
 // Rows larger than the 256 MiB last-level cache are streamed with
 // non-temporal loads; smaller ones stay cached between passes.
 constexpr int64_t kCachedRowBytes = 256ll << 20;
-
-struct SeedLayout {
-  size_t tsum, tsum2, D, D2, idx, total;  // tsum2, D2: the second buffers of the draw at pass start
-};
-
-SeedLayout seed_layout(int64_t N, int K) {
-  SeedLayout L;
-  size_t off = sizeof(Ctl);
-  const size_t tiles = align256(sizeof(double) * (size_t)std::min<int64_t>(N, kMaxTiles));
-  L.tsum = off;
-  off += tiles;
-  L.tsum2 = off;
-  off += tiles;
-  L.D = off;
-  off += align256(sizeof(float) * (size_t)N);
-  L.D2 = off;
-  off += align256(sizeof(float) * (size_t)N);
-  L.idx = off;
-  off += align256(sizeof(int64_t) * (size_t)K);
-  L.total = off;
-  return L;
-}
 
 const SeedVariant* pick_seed_variant(int dtype, int d, int nt, int u, int rl, int cs) {
   const auto& vs = seed_variants();
@@ -171,6 +148,7 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   p.seed = seed;
   p.wts = wts;
   p.tag = tag;
+  p.sumD = opts ? opts->out_sumD : nullptr;
   // the draw at pass start (unweighted seeding, exact-width passes): every
   // workgroup reads all tile sums, so their number is bounded, and its LDS
   // staging must leave the pass's occupancy alone (160 KiB of LDS per CU,

@@ -36,6 +36,7 @@ struct SeedParams {
   uint32_t tag;          // Philox counter word 3 of the draws (0: the k-means++ stream)
   float* Dw;             // draw at pass start: this pass's D (every row; D holds the previous pass's)
   double* tsum_w;        // draw at pass start: this pass's tile sums (tsum holds the previous pass's)
+  double* sumD;          // [K] or null: the FP64 sum of D each draw inverted
 };
 
 // One compiled seed-pass kernel.
@@ -61,6 +62,32 @@ int seed_draw_threads();
 // Maximum number of tiles of one pass; bounds the tile-sum scan of the draw
 // and the workspace.
 constexpr int64_t kMaxTiles = 8192;  // = draw threads (256) x tile sums per thread (32)
+
+// Workspace of one seeding run: the control block, two FP64 tile-sum
+// buffers, two D buffers (the second and the second tile sums only for the
+// draw at pass start) and the indices.
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct SeedLayout {
+  size_t tsum, tsum2, D, D2, idx, total;  // tsum2, D2: the second buffers of the draw at pass start
+};
+constexpr SeedLayout seed_layout(int64_t N, int64_t K) {
+  SeedLayout L{};
+  size_t off = 256;  // the control block (Ctl)
+  const size_t tiles = align256(sizeof(double) * (size_t)(N < kMaxTiles ? N : kMaxTiles));
+  L.tsum = off;
+  off += tiles;
+  L.tsum2 = off;
+  off += tiles;
+  L.D = off;
+  off += align256(sizeof(float) * (size_t)N);
+  L.D2 = off;
+  off += align256(sizeof(float) * (size_t)N);
+  L.idx = off;
+  off += align256(sizeof(int64_t) * (size_t)K);
+  L.total = off;
+  return L;
+}
 
 // One k-means++ run (init, K passes, K-1 draws) on the stream; weighted when
 // wts is non-null (the first draw proportional to w, then to w * D).

@@ -36,6 +36,7 @@ __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
   if (threadIdx.x == 0) {
     p.ctl->status = KMPP_OK;
     p.ctl->arrive = 0u;
+    if (p.sumD) p.sumD[0] = 0.0;
     const double u0 = draw_uniform(p.seed, 0u, p.inst);
     const int64_t i0 = uniform_index(u0, p.N);
     p.idx[0] = i0;
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(kDrawNT) void seed_draw_kernel(SeedParams p) {
   const double2 sc = draw_scan<NT>(part, sh);
   const double T = sc.y;
   const double u = draw_uniform(p.seed, (uint32_t)p.pass, p.inst, p.tag);
+  if (tid == 0 && p.sumD) p.sumD[p.pass] = T;
 
   int64_t seed_row;
   if (!isfinite(T)) {
@@ -317,6 +319,7 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
   const double2 sc = draw_scan<NT>(part, sh);
   const double T = sc.y;
   const double u = draw_uniform(p.seed, (uint32_t)step, p.inst, p.tag);
+  if (lead && tid == 0 && p.sumD) p.sumD[step] = T;
 
   int64_t seed_row;
   if (!isfinite(T)) {

@@ -115,7 +115,8 @@ def test_full_batched_workload(kl):
     print("batched workload 512 instances", flush=True)
     outs, ws = kl.kmpp_seed_batched(Xs, spec.K, 0)
     assert kl.kmpp_status(ws) == 0
-    # every instance: structural properties; a spread sample: full replay
+    # every instance: structural properties, then the oracle replay of every
+    # draw and the final D of every row
     for b in range(512):
         C, D, I = outs[b]
         idx = I.cpu().numpy()
@@ -123,9 +124,9 @@ def test_full_batched_workload(kl):
         assert len(set(idx.tolist())) == spec.K[b]
         assert torch.all(D[I] == 0).item()
         assert torch.equal(C, Xs[b][I])
-    order = np.argsort([spec.N[b] * spec.d[b] * spec.K[b] for b in range(512)])
-    sample = list(order[:4]) + list(order[-4:]) + list(order[250:254])
-    _check_all(Xs, spec.K, outs, 0, which=[int(b) for b in sample])
+    for b0 in range(0, 512, 64):
+        _check_all(Xs, spec.K, outs, 0, which=range(b0, b0 + 64))
+        print(f"  instances {b0}..{b0 + 63} replayed", flush=True)
 
 
 def test_rejects_bad_instances(kl):
