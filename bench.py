@@ -1,48 +1,54 @@
 #!/usr/bin/env python3
 """Benchmark of the k-means++ hot path on one MI355X.
 
-A step is one full k-means++ run on the N=1,000,000, d=32, K=256
-Gaussian-mixture workload: the seed loop (K passes over the rows, K-1
-draws) followed by the nearest-seed assignment.  Inputs are synthetic,
-seeded, and resident in HBM before the timed region.  Prints ONE JSON line.
+A step is one full k-means++ run on the N=16,777,216, d=64, K=4096
+Student-t mixture workload in FP32 (the largest single-GPU shape): the seed
+loop (K passes over the 4 GiB of rows, K-1 draws) followed by the
+nearest-seed assignment of every row.  Inputs are synthetic, seeded, and
+resident in HBM before the timed region.  Prints ONE JSON line.
 
   value         point-seed distances per second over the whole step,
                 N*K / t_step
-  roofline      the seed-pass kernel: algorithmic row bytes per launch
-                (N*d*4) over its average launch duration, from HIP events
-                attached to every pass launch on its stream (start and stop
-                of the kernel itself; a second timed run of the same step);
-                `attainable` is the library's read probe on a buffer of the
-                bytes one pass reads (rows and D), re-read back to back
-  device        GPU name, architecture, compute units, HIP version
+  roofline      the seed-pass kernel (d = 64, FP32): algorithmic row bytes
+                per launch (N*d*4 = 4.295 GB) over its average launch
+                duration, from HIP events attached to every pass launch on
+                its stream (a separate seeding run of the same step);
+                `traffic`: HBM bytes per launch from the committed rocprofv3
+                FETCH_SIZE / WRITE_SIZE summary while the kernel sources
+                match it (else null); `attainable`: the library's read probe
+                on a buffer of the bytes one pass reads (rows and D, 4.36 GB,
+                far beyond the 256 MiB last-level cache)
+  assign_roofline  the assignment of the same step against FP32 MFMA peak
+  cpu_baseline  the FP64 oracle on all host cores, a bounded sample of the
+                same step (the first passes of the seeding on all rows and
+                the assignment of sampled rows), scaled to the whole step
+                and labelled extrapolated; cpu_baseline_1core: one core
+  plain         the N=1,000,000, d=32, K=256 step (its rows fit the
+                last-level cache, so its pass rate is not an HBM figure)
   small         the 10,000 x 2, K=16 workload (latency-bound): us per
                 seeding run and per seeding + assignment step
-  cpu_baseline  the FP64 oracle on the host cores, the same step on the
-                same rows (repeated to about 10 s of CPU work), same unit;
-                cpu_baseline_1core: the oracle on one core, 16 seeds
-  ms_per_step_min / _median, cold_first_step_ms: per-step timings of the
-                same step (a second loop) and the process's first step
   forms         the precision forms (BF16 / per-row FP8 rows) on the
                 4,194,304 x 128 (K=1024) and 16,777,216 x 64 (K=4096)
-                workloads, and the batched form (512 uneven instances in one
-                persistent launch) against 512 plain calls; --no-forms skips
-                them
-  lloyd         Lloyd iterations after seeding (per-iteration time, the
-                centre update alone); --no-lloyd skips them
-  kmeans_parallel  k-means|| (Bahmani et al.) against k-means++ on the same
-                rows: time and cost of the K centres; --no-kmpar skips it
-  memory_spaces the paper's memory-space comparison (Section II, Figs. 2c
-                and 3c) on this chip: every row path (cached, non-temporal,
-                buffer descriptor) x centre source (LDS, scalar, global) on
-                the paper's 2-D shapes and on 32- and 128-wide rows;
-                --no-spaces skips it
+                workloads with their error statement against the FP64 oracle
+                on the FP32 rows (cost ratio over several Philox seeds,
+                per-draw relative error of the sum of D and draw agreement on
+                a replayed prefix, the FP32 recheck of the drawn rows), and
+                the batched form (512 uneven instances in one persistent
+                launch) against 512 plain calls; --no-forms skips them
+  lloyd, kmeans_parallel, memory_spaces  the steps around the path (Lloyd
+                iterations, k-means||, the paper's memory-space comparison);
+                --no-lloyd / --no-kmpar / --no-spaces skip them
 
+--step-only runs the headline step alone (for profiler runs);
+--assign-only CASE runs four assignments of one case and exits (counter
+collection: plain-f32, unitsphere-f32, unitsphere-bf16, unitsphere-fp8).
 Only one GPU is used; --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -123,128 +129,6 @@ def seed_pass_rate(kl, X, K, row_bytes, reps=2, **kw):
         durs += ev.pass_ms()
     avg = float(np.mean(durs))
     return avg, row_bytes / (avg * 1e-3) / 1e9
-
-
-PMC_PROFILE = os.path.join(ROOT, "profiles", "seed_pass_f32_d32_gaussian1M_pmc.md")
-PMC_SOURCES = ["paper_1908_02136_amd/csrc/seed.hip", "paper_1908_02136_amd/csrc/stream.h",
-               "paper_1908_02136_amd/csrc/kmpp_dev.h", "paper_1908_02136_amd/tune_table.txt"]
-
-
-def profiled_traffic():
-    """HBM bytes per seed-pass launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None if
-    the kernel sources or schedules changed since the counters were taken."""
-    import hashlib
-    try:
-        txt = open(PMC_PROFILE).read()
-        want = txt.split("source_sha256:")[1].split()[0]
-        traffic = float(txt.split("traffic_bytes_per_launch:")[1].split()[0])
-        h = hashlib.sha256()
-        for f in PMC_SOURCES:
-            with open(os.path.join(ROOT, f), "rb") as fh:
-                h.update(fh.read())
-    except (OSError, IndexError, ValueError):
-        return None
-    return traffic if h.hexdigest() == want else None
-
-
-def cpu_baseline(Xh: np.ndarray, K: int, budget_s: float = 10.0, max_reps: int = 5):
-    """The FP64 oracle as it stands, on all host cores: the same step (full
-    seeding, K passes, then the assignment of every row to the oracle's own
-    seeds) on the same rows, repeated until about `budget_s` of CPU work;
-    value in the bench's unit, N*K per step-second."""
-    import oracle
-    cores = len(os.sched_getaffinity(0))
-    N = Xh.shape[0]
-    times, ts_seed, ts_assign = [], [], []
-    while len(times) < max_reps and sum(times) < budget_s:
-        t0 = time.perf_counter()
-        r = oracle.seed(Xh, K, seed=0, nthreads=cores)
-        t1 = time.perf_counter()
-        oracle.assign(Xh, Xh[r.idx], nthreads=cores)
-        t2 = time.perf_counter()
-        ts_seed.append(t1 - t0)
-        ts_assign.append(t2 - t1)
-        times.append(t2 - t0)
-    t = float(np.mean(times))
-    return {"value": N * K / t, "unit": "point-seed dists/s", "cores": cores, "kind": "oracle",
-            "sample": f"the whole step on the same {N}x{Xh.shape[1]} rows (FP64 seeding, {K} passes: "
-                      f"{np.mean(ts_seed):.2f} s; FP64 assignment of all rows: {np.mean(ts_assign):.2f} s), "
-                      f"{len(times)} repetitions, {cores} threads"}
-
-
-def cpu_baseline_1core(Xh: np.ndarray, K: int = 16):
-    """The FP64 oracle on one core (the paper's CPU baseline is serial): the
-    same kind of step, K seeds on the same rows, value N*K per step-second."""
-    import oracle
-    N = Xh.shape[0]
-    t0 = time.perf_counter()
-    r = oracle.seed(Xh, K, seed=0, nthreads=1)
-    t1 = time.perf_counter()
-    oracle.assign(Xh, Xh[r.idx], nthreads=1)
-    t2 = time.perf_counter()
-    return {"value": N * K / (t2 - t0), "unit": "point-seed dists/s", "cores": 1, "kind": "oracle",
-            "sample": f"{K} seeds on the same {N}x{Xh.shape[1]} rows (FP64 seeding {t1 - t0:.2f} s, "
-                      f"assignment {t2 - t1:.2f} s), one thread"}
-
-
-def precision_forms(kl, name, w, reps):
-    """FP32 vs BF16 (vs FP8) seeding and assignment on one workload."""
-    X, N, d, K = w.X, w.N, w.d, w.K
-    res = {"workload": f"{name} N={N} d={d} K={K}"}
-    forms = [("f32", kl.KMPP_F32)] + [("bf16", kl.KMPP_BF16)] + ([("fp8", kl.KMPP_FP8_E4M3)] if d <= 128 else [])
-    phi = {}
-    for tag, dt in forms:
-        if dt == kl.KMPP_F32:
-            Xq = E = None
-            qms = 0.0
-        else:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            Xq, E = kl.kmpp_quantize(X, dt)
-            torch.cuda.synchronize()
-            qms = (time.perf_counter() - t0) * 1e3
-        elem = {"f32": 4, "bf16": 2, "fp8": 1}[tag]
-        row_bytes = N * d * elem + (N if tag == "fp8" else 0)
-        rec = torch.zeros(2 * K, device="cuda")
-        out = {}
-
-        def run():
-            out["r"] = kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dt, out_recheck=rec if dt else None)
-
-        run()
-        torch.cuda.synchronize()
-        ms = time_events(run, reps)
-        idx, C, D, ws = out["r"]
-        st = kl.kmpp_status(ws)
-        pms, pgbs = seed_pass_rate(kl, X, K, row_bytes, reps=1, Xq=Xq, Xq_exp=E, dtype=dt)
-        Xa = X if dt == kl.KMPP_F32 else Xq
-        kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt)
-        torch.cuda.synchronize()
-        ams = time_events(lambda: kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt), reps)
-        flops = 2.0 * N * K * d
-        # BF16 / FP8 rows take two products (centre high part and remainder)
-        executed = flops * (1 if dt == kl.KMPP_F32 else 2)
-        peak = MFMA_PEAK_TFLOPS["f32" if dt == kl.KMPP_F32 else "bf16"]
-        phi[tag] = float(D.double().sum().item())
-        entry = {"seed_ms": ms, "status": st, "dists_per_s": N * K / (ms * 1e-3),
-                 "seed_GBps": row_bytes * K / (ms * 1e-3) / 1e9,
-                 "pass_us": pms * 1e3, "pass_GBps": pgbs, "pass_frac_hbm": pgbs / HBM_PEAK_GBS,
-                 "assign_ms": ams, "assign_TFLOPs": flops / (ams * 1e-3) / 1e12,
-                 "assign_frac_mfma": executed / (ams * 1e-3) / 1e12 / peak, "quantize_ms": qms,
-                 "phi": phi[tag]}
-        if dt:
-            r = rec.view(K, 2)[1:].double()
-            ratio = (r[:, 0] / r[:, 1].clamp_min(1e-30)).cpu().numpy()
-            entry["recheck_ratio_median"] = float(np.median(ratio))
-            entry["recheck_ratio_p99"] = float(np.quantile(np.abs(ratio - 1), 0.99))
-            entry["phi_vs_f32"] = phi[tag] / phi["f32"]
-        res[tag] = entry
-        _log(f"  {name} {tag}: seed {ms:.1f} ms ({entry['dists_per_s']:.3g} dists/s), pass {pms*1e3:.1f} us "
-             f"{pgbs:.0f} GB/s, assign {ams:.2f} ms {entry['assign_TFLOPs']:.1f} TF/s, status {st}")
-        del Xq, E, out, C, D
-        torch.cuda.empty_cache()
-    return res
 
 
 def batched_form(kl, reps):
@@ -449,16 +333,287 @@ def small_latency(kl, kmpp_synth, reps=50):
             "status": kl.kmpp_status(ws)}
 
 
+
+
+MFMA_PEAK_TFLOPS["fp8"] = 5000.0   # dense FP8 matrix peak: the ceiling FP8 rows are judged against
+
+
+SEED_SOURCES = ["paper_1908_02136_amd/csrc/seed.hip", "paper_1908_02136_amd/csrc/stream.h",
+                "paper_1908_02136_amd/csrc/kmpp_dev.h", "paper_1908_02136_amd/tune_table.txt"]
+
+
+def profiled_traffic(profile: str, sources=SEED_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None if the
+    kernel sources or schedules changed since the counters were taken."""
+    try:
+        txt = open(os.path.join(ROOT, "profiles", profile)).read()
+        want = txt.split("source_sha256:")[1].split()[0]
+        traffic = float(txt.split("traffic_bytes_per_launch:")[1].split()[0])
+        h = hashlib.sha256()
+        for f in sources:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, IndexError, ValueError):
+        return None
+    return traffic if h.hexdigest() == want else None
+
+
+def _cores():
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(Xh: np.ndarray, K: int, C: np.ndarray, passes: int = 96, rows: int = 131_072,
+                 nthreads: int = 0):
+    """The FP64 oracle as it stands on a bounded sample of the step: its
+    first `passes` seed passes (passes - 1 draws) on all rows, scaled by
+    K / passes (every pass costs the same), and the assignment of `rows`
+    sampled rows against the step's K centres, scaled by N / rows; value in
+    the bench's unit, N*K per extrapolated step-second."""
+    import oracle
+    cores = nthreads if nthreads > 0 else _cores()
+    N, d = Xh.shape
+    passes = min(passes, K)
+    t0 = time.perf_counter()
+    oracle.seed(Xh, passes, seed=0, nthreads=cores)
+    t1 = time.perf_counter()
+    sel = np.random.default_rng(0).choice(N, min(rows, N), replace=False)
+    Xs = np.ascontiguousarray(Xh[sel])
+    t2 = time.perf_counter()
+    oracle.assign(Xs, C, nthreads=cores)
+    t3 = time.perf_counter()
+    t_seed = (t1 - t0) * K / passes
+    t_assign = (t3 - t2) * N / sel.size
+    t = t_seed + t_assign
+    return {"value": N * K / t, "unit": "point-seed dists/s", "cores": cores, "kind": "oracle",
+            "extrapolated": True,
+            "sample": f"FP64 oracle on {N}x{d} rows, {cores} threads: the first {passes} of {K} seed passes "
+                      f"({t1 - t0:.2f} s, scaled by {K}/{passes} to {t_seed:.1f} s) and the assignment of "
+                      f"{sel.size} sampled rows to the {K} centres ({t3 - t2:.2f} s, scaled by N/{sel.size} "
+                      f"to {t_assign:.1f} s); whole step extrapolated to {t:.1f} s"}
+
+
+def timed_steps(step, steps, warmup):
+    """The contract's timed region: `warmup` untimed steps, then exactly
+    `steps` steps between two synchronisations; events between the steps
+    give the per-step spread without extra synchronisation."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step()
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return float(np.sum(per)) / steps, per, wall
+
+
+def elem_bytes(tag):
+    return {"f32": 4, "bf16": 2, "fp8": 1}[tag]
+
+
+def form_entry(kl, name, w, tag, reps, X_host=None):
+    """Seeding and assignment of one storage form of a workload."""
+    X, N, d, K = w.X, w.N, w.d, w.K
+    dt = kl.DTYPES[tag]
+    Xq = E = None
+    qms = 0.0
+    if dt:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xq, E = kl.kmpp_quantize(X, dt)
+        torch.cuda.synchronize()
+        qms = (time.perf_counter() - t0) * 1e3
+    row_bytes = N * d * elem_bytes(tag) + (N if tag == "fp8" else 0)
+    out = {}
+
+    def run():
+        out["r"] = kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dt)
+
+    run()
+    torch.cuda.synchronize()
+    ms = time_events(run, reps)
+    idx, C, D, ws = out["r"]
+    st = kl.kmpp_status(ws)
+    pms, pgbs = seed_pass_rate(kl, X, K, row_bytes, reps=1, Xq=Xq, Xq_exp=E, dtype=dt)
+    Xa = X if dt == kl.KMPP_F32 else Xq
+    kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt)
+    torch.cuda.synchronize()
+    ams = time_events(lambda: kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt), max(reps, 3))
+    flops = 2.0 * N * K * d
+    tf = flops / (ams * 1e-3) / 1e12
+    entry = {"seed_ms": ms, "status": st, "dists_per_s": N * K / (ms * 1e-3),
+             "seed_GBps": row_bytes * K / (ms * 1e-3) / 1e9,
+             "pass_us": pms * 1e3, "pass_GBps": pgbs, "pass_frac_hbm": pgbs / HBM_PEAK_GBS,
+             "assign_ms": ams, "assign_TFLOPs": tf, "assign_peak_TFLOPs": MFMA_PEAK_TFLOPS[tag],
+             "assign_frac_mfma": tf / MFMA_PEAK_TFLOPS[tag], "quantize_ms": qms,
+             "phi_seed0": float(D.double().sum().item())}
+    _log(f"  {name} {tag}: seed {ms:.1f} ms ({entry['dists_per_s']:.3g} dists/s), pass {pms*1e3:.1f} us "
+         f"{pgbs:.0f} GB/s, assign {ams:.2f} ms {tf:.1f} TF/s ({entry['assign_frac_mfma']:.3f} of "
+         f"{MFMA_PEAK_TFLOPS[tag]:.0f}), status {st}")
+    return entry, (Xq, E)
+
+
+def f32_phis(kl, w, seeds=5):
+    """Sum of the final D of the FP32 form for Philox seeds 0..seeds-1."""
+    out = []
+    for s in range(seeds):
+        _, _, Df, _ = kl.kmpp_seed(w.X, w.K, s)
+        out.append(float(Df.double().sum().item()))
+    return out
+
+
+def precision_error(kl, name, w, Xh, q, tag, phi_f32, prefix=64, cores=0):
+    """Error of a storage form against the FP64 oracle on the FP32 rows.
+      phi ratio     sum of the final D (from the stored rows) over the FP32
+                    form's, same Philox seed, mean and sd over `seeds` seeds
+                    (the seeds of the two forms drift apart after the first
+                    draws, so this compares outcomes, not draw by draw);
+      sumD rel err  |sum D_gpu - sum D_oracle| / sum D_oracle at each of the
+                    first `prefix` draws, the oracle replaying the stored
+                    form's own seeds on the FP32 rows;
+      draw agreement  the fraction of those draws that the oracle on the
+                    FP32 rows makes the same (or accepts within the boundary
+                    tolerance) from the same earlier seeds;
+      recheck ratio  D of each drawn row from the stored rows over its FP32
+                    nearest distance from the original row (all K-1 draws)."""
+    import oracle
+    X, N, d, K = w.X, w.N, w.d, w.K
+    Xq, E = q
+    dt = kl.DTYPES[tag]
+    seeds = len(phi_f32)
+    ratios = []
+    for s in range(seeds):
+        _, _, Dq, _ = kl.kmpp_seed(X, K, s, Xq=Xq, Xq_exp=E, dtype=dt)
+        ratios.append(float(Dq.double().sum().item()) / phi_f32[s])
+    rec = torch.zeros(2 * K, device="cuda")
+    sumD = torch.zeros(K, dtype=torch.float64, device="cuda")
+    idx, _, _, _ = kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dt, out_recheck=rec, out_sumD=sumD)
+    torch.cuda.synchronize()
+    idx_h, sum_h = idx.cpu().numpy(), sumD.cpu().numpy()
+    r2 = rec.view(K, 2)[1:].double().cpu().numpy()
+    P = min(K, prefix + 1)
+    r = oracle.seed(Xh, P, seed=0, replay=idx_h[:P], nthreads=cores)
+    T = r.rec[1:P, oracle.REC_T]
+    rel = np.abs(sum_h[1:P] - T) / T
+    agree = [int(idx_h[m]) == int(r.idx[m]) or oracle.seed_index_ok(int(idx_h[m]), r.rec[m], int(r.idx[m]))
+             for m in range(1, P)]
+    ratio = r2[:, 0] / np.maximum(r2[:, 1], 1e-30)
+    res = {"phi_ratio_mean": float(np.mean(ratios)), "phi_ratio_sd": float(np.std(ratios, ddof=1)),
+           "phi_ratio_seeds": seeds, "phi_ratios": ratios,
+           "sumD_rel_err_median": float(np.median(rel)), "sumD_rel_err_max": float(np.max(rel)),
+           "replayed_draws": P - 1, "draw_agreement": float(np.mean(agree)),
+           "recheck_ratio_median": float(np.median(ratio)),
+           "recheck_ratio_p99_dev": float(np.quantile(np.abs(ratio - 1.0), 0.99))}
+    _log(f"  {name} {tag} error: phi ratio {res['phi_ratio_mean']:.4f} +- {res['phi_ratio_sd']:.4f} "
+         f"({seeds} seeds), sumD rel err median {res['sumD_rel_err_median']:.2e} max {res['sumD_rel_err_max']:.2e}, "
+         f"draw agreement {res['draw_agreement']:.3f} over {P - 1} draws, recheck ratio median "
+         f"{res['recheck_ratio_median']:.4f}")
+    return res
+
+
+def forms_section(kl, kmpp_synth, large_w, large_Xh, large_f32, reps=2):
+    """The precision forms on the 4.2M x 128 and 16.7M x 64 workloads (the
+    latter's FP32 entry is the headline run), with their error statement."""
+    cores = _cores()
+    out = {}
+    wu = kmpp_synth.unitsphere(device="cuda")
+    Xuh = wu.X.cpu().numpy()
+    ent = {"workload": f"unitsphere N={wu.N} d={wu.d} K={wu.K}"}
+    ent["f32"], _ = form_entry(kl, "unitsphere", wu, "f32", reps)
+    phis = f32_phis(kl, wu)
+    for tag in ("bf16", "fp8"):
+        ent[tag], q = form_entry(kl, "unitsphere", wu, tag, reps)
+        ent[tag]["error"] = precision_error(kl, "unitsphere", wu, Xuh, q, tag, phis, cores=cores)
+        del q
+    out["unitsphere"] = ent
+    del wu, Xuh
+    torch.cuda.empty_cache()
+    ent = {"workload": f"large N={large_w.N} d={large_w.d} K={large_w.K}", "f32": large_f32}
+    phis = f32_phis(kl, large_w)
+    for tag in ("bf16", "fp8"):
+        ent[tag], q = form_entry(kl, "large", large_w, tag, 1)
+        ent[tag]["error"] = precision_error(kl, "large", large_w, large_Xh, q, tag, phis, cores=cores)
+        del q
+        torch.cuda.empty_cache()
+    out["large"] = ent
+    return out
+
+
+def plain_step(kl, kmpp_synth, steps):
+    """The 1,000,000 x 32, K=256 step: its 128 MB of rows stay in the 256 MiB
+    last-level cache between passes, so its pass rate is a cache figure."""
+    w = kmpp_synth.plain(device="cuda")
+    X, N, d, K = w.X, w.N, w.d, w.K
+    C = torch.empty((K, d), device="cuda")
+    idx = torch.empty(K, dtype=torch.int64, device="cuda")
+    D = torch.empty(N, device="cuda")
+    lab = torch.empty(N, dtype=torch.int32, device="cuda")
+    mind = torch.empty(N, device="cuda")
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, K), "cuda")
+    wa = kl.workspace(kl.kmpp_assign_workspace_bytes(N, d, K), "cuda")
+
+    def seed():
+        kl.kmpp_seed(X, K, 0, out_centers=C, out_D=D, out_idx=idx, ws=ws)
+
+    def step():
+        seed()
+        kl.kmpp_assign(X, C, out_labels=lab, out_mind=mind, ws=wa)
+
+    ms, per, _ = timed_steps(step, steps, 2)
+    seed_ms = time_events(seed, 5)
+    pass_ms, pass_gbs = seed_pass_rate(kl, X, K, N * d * 4)
+    res = {"workload": f"plain N={N} d={d} K={K} FP32 (rows resident in the last-level cache)",
+           "ms_per_step": ms, "dists_per_s": N * K / (ms * 1e-3), "ms_per_step_min": float(np.min(per)),
+           "seed_ms": seed_ms, "seed_loop_GBps": N * d * 4 * K / (seed_ms * 1e-3) / 1e9,
+           "pass_us": pass_ms * 1e3, "pass_GBps": pass_gbs, "llc_resident": True,
+           "pass_traffic": profiled_traffic("seed_pass_f32_d32_gaussian1M_pmc.md"),
+           "status": kl.kmpp_status(ws)}
+    _log(f"plain: step {ms:.3f} ms, seed {seed_ms:.3f} ms, pass {pass_ms*1e3:.1f} us {pass_gbs:.0f} GB/s")
+    return res, w
+
+
+ASSIGN_CASES = {
+    "plain-f32": (1_000_000, 32, 256, "f32"),
+    "unitsphere-f32": (4_194_304, 128, 1024, "f32"),
+    "unitsphere-bf16": (4_194_304, 128, 1024, "bf16"),
+    "unitsphere-fp8": (4_194_304, 128, 1024, "fp8"),
+    "large-f32": (16_777_216, 64, 4096, "f32"),
+}
+
+
+def assign_only(kl, case):
+    """Counter-collection driver: N(0, 1) rows, the first K rows as centres,
+    one untimed and three more assignments."""
+    N, d, K, tag = ASSIGN_CASES[case]
+    g = torch.Generator(device="cuda").manual_seed(1)
+    X = torch.randn((N, d), device="cuda", generator=g)
+    C = X[:K].contiguous()
+    dt = kl.DTYPES[tag]
+    Xq, E = (X, None) if dt == kl.KMPP_F32 else kl.kmpp_quantize(X, dt)
+    for _ in range(4):
+        kl.kmpp_assign(Xq, C, X_exp=E, dtype=dt)
+    torch.cuda.synchronize()
+    print("assign-only done", case, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched forms")
     ap.add_argument("--no-spaces", action="store_true", help="skip the memory-space comparison")
     ap.add_argument("--no-lloyd", action="store_true", help="skip the Lloyd iterations")
     ap.add_argument("--no-kmpar", action="store_true", help="skip the k-means|| comparison")
+    ap.add_argument("--step-only", action="store_true", help="the headline step alone (profiler runs)")
+    ap.add_argument("--assign-only", default=None, choices=sorted(ASSIGN_CASES),
+                    help="four assignments of one case, then exit (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
@@ -472,6 +627,9 @@ def main():
     import paper_1908_02136_amd as kl
     kl.lib()
     torch.cuda.set_device(0)
+    if args.assign_only:
+        assign_only(kl, args.assign_only)
+        return
 
     # a plain device copy of known size (256 MiB read, 256 MiB written):
     # the reference that scales the HBM byte counters of a profiled run
@@ -480,9 +638,9 @@ def main():
     cal_dst.copy_(cal)
     del cal, cal_dst
 
-    w = kmpp_synth.plain(device="cuda")
+    w = kmpp_synth.large(device="cuda")
     X, N, d, K = w.X, w.N, w.d, w.K
-    _log(f"workload plain N={N} d={d} K={K}")
+    _log(f"workload large N={N} d={d} K={K} FP32")
     out_idx = torch.empty(K, dtype=torch.int64, device="cuda")
     out_C = torch.empty((K, d), dtype=torch.float32, device="cuda")
     out_D = torch.empty(N, dtype=torch.float32, device="cuda")
@@ -502,25 +660,16 @@ def main():
         assign()
 
     cold_ms = time_events(step, 1)  # the first step of the process: code objects load here
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ms = time_events(step, args.steps)
-    torch.cuda.synchronize()
-    per_step = [time_events(step, 1) for _ in range(args.steps)]
+    ms, per_step, wall_ms = timed_steps(step, args.steps, args.warmup)
     status = kl.kmpp_status(ws)
-    seed_ms = time_events(seed, max(2, args.steps // 2))
-    assign_ms = time_events(assign, max(2, args.steps // 2))
-    _log(f"step {ms:.3f} ms (seed {seed_ms:.3f}, assign {assign_ms:.3f})  status {status}")
+    seed_ms = time_events(seed, 2)
+    assign_ms = time_events(assign, 3)
+    _log(f"step {ms:.2f} ms (seed {seed_ms:.2f}, assign {assign_ms:.2f}), status {status}")
 
     row_bytes = N * d * 4
-    pass_ms, pass_gbs = seed_pass_rate(kl, X, K, row_bytes)
-    # the pass reads the rows and D (4 B per row), re-read pass after pass
-    probe_gbs, probe_how = read_probe(kl, row_bytes + 4 * N)
-    _log(f"read probe ({(row_bytes + 4 * N) / 1e6:.0f} MB re-read): {probe_gbs:.0f} GB/s {probe_how}")
+    pass_ms, pass_gbs = seed_pass_rate(kl, X, K, row_bytes, reps=1)
     _log(f"seed pass avg {pass_ms * 1e3:.1f} us  {pass_gbs:.0f} GB/s")
     aflops = 2.0 * N * K * d
-
     res = {
         "metric": "k-means++ point-seed dists/s",
         "value": N * K / (ms * 1e-3),
@@ -534,52 +683,72 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "gaussian-mixture seeding + assignment, N=1000000 d=32 K=256 (256 components, "
-                               "Dirichlet weights), FP32", "N": N, "d": d, "K": K},
+        "config": {"workload": "large: k-means++ seeding + assignment, N=16777216 d=64 K=4096, 4096-component "
+                               "mixture with Student-t (nu=3) noise, means U[-100,100]^64, FP32 rows",
+                   "N": N, "d": d, "K": K},
         "ms_per_step_min": float(np.min(per_step)),
         "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step_wall": wall_ms,
         "cold_first_step_ms": cold_ms,
         "seed_ms": seed_ms,
         "assign_ms": assign_ms,
         "seed_loop_GBps": row_bytes * K / (seed_ms * 1e-3) / 1e9,
+        "seed_loop_frac_hbm": row_bytes * K / (seed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": pass_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(),
-                     "kernel": "seed_pass_kernel<F32, d=32>", "avg_launch_us": pass_ms * 1e3,
-                     "bytes_per_launch": row_bytes, "attainable": probe_gbs,
-                     "frac_attainable": pass_gbs / probe_gbs, "attainable_probe": probe_how},
+                     "frac": pass_gbs / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("seed_pass_f32_d64_large16M_pmc.md"),
+                     "kernel": "seed_pass_kernel<F32, d=64>", "avg_launch_us": pass_ms * 1e3,
+                     "bytes_per_launch": row_bytes},
         "assign_roofline": {"bound": "mfma", "achieved": aflops / (assign_ms * 1e-3) / 1e12,
                             "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                            "frac": aflops / (assign_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"]},
+                            "frac": aflops / (assign_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"],
+                            "flops_per_call": aflops},
+        "status": status,
     }
     props = torch.cuda.get_device_properties(0)
     res["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
                      "compute_units": props.multi_processor_count, "hip": torch.version.hip}
-    del ws, wa
-    res["small"] = small_latency(kl, kmpp_synth)
-    _log(f"small: seed {res['small']['seed_us']:.1f} us, step {res['small']['step_us']:.1f} us")
+    if args.step_only:
+        print(json.dumps(res), flush=True)
+        return
+    # the pass reads the rows and D (4 B per row), far beyond the last-level cache
+    probe_gbs, probe_how = read_probe(kl, row_bytes + 4 * N, reps=5)
+    res["roofline"]["attainable"] = probe_gbs
+    res["roofline"]["frac_attainable"] = pass_gbs / probe_gbs
+    res["roofline"]["attainable_probe"] = dict(probe_how, bytes=row_bytes + 4 * N)
+    _log(f"read probe ({(row_bytes + 4 * N) / 1e9:.2f} GB): {probe_gbs:.0f} GB/s {probe_how}")
+    large_f32 = {"seed_ms": seed_ms, "pass_us": pass_ms * 1e3, "pass_GBps": pass_gbs,
+                 "pass_frac_hbm": pass_gbs / HBM_PEAK_GBS, "assign_ms": assign_ms,
+                 "assign_TFLOPs": res["assign_roofline"]["achieved"], "assign_peak_TFLOPs": MFMA_PEAK_TFLOPS["f32"],
+                 "assign_frac_mfma": res["assign_roofline"]["frac"], "dists_per_s": N * K / (seed_ms * 1e-3),
+                 "phi_seed0": float(out_D.double().sum().item())}
+    C_h = out_C.cpu().numpy()
+    del ws, wa, lab, mind
+    torch.cuda.empty_cache()
+    Xh = X.cpu().numpy() if (not args.no_forms or not args.no_cpu_baseline) else None
+
     if not args.no_forms:
-        reps = 2
-        forms = {}
-        for name, fn in [("unitsphere", kmpp_synth.unitsphere), ("large", kmpp_synth.large)]:
-            wf = fn(device="cuda")
-            forms[name] = precision_forms(kl, name, wf, reps)
-            del wf
-            torch.cuda.empty_cache()
+        forms = forms_section(kl, kmpp_synth, w, Xh, large_f32)
         forms["batched"] = batched_form(kl, reps=3)
         res["forms"] = forms
+    del w, X, out_D
+    torch.cuda.empty_cache()
+    res["plain"], wp = plain_step(kl, kmpp_synth, max(5, args.steps))
+    res["small"] = small_latency(kl, kmpp_synth)
+    _log(f"small: seed {res['small']['seed_us']:.1f} us, step {res['small']['step_us']:.1f} us")
     if not args.no_lloyd:
-        res["lloyd"] = [lloyd_iterations(kl, "plain", w, iters=10)]
+        res["lloyd"] = [lloyd_iterations(kl, "plain", wp, iters=10)]
         wu = kmpp_synth.unitsphere(device="cuda")
         res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3))
         res["lloyd"].append(lloyd_iterations(kl, "unitsphere", wu, iters=3, dtype=kl.KMPP_BF16))
         del wu
         torch.cuda.empty_cache()
     if not args.no_kmpar:
-        res["kmeans_parallel"] = [kmeans_parallel(kl, "plain", w)]
+        res["kmeans_parallel"] = [kmeans_parallel(kl, "plain", wp)]
         for nm in ("paper_k", "paper_n"):
-            wp = kmpp_synth.paper_shape(nm, device="cuda")
-            res["kmeans_parallel"].append(kmeans_parallel(kl, nm, wp))
-            del wp
+            wpp = kmpp_synth.paper_shape(nm, device="cuda")
+            res["kmeans_parallel"].append(kmeans_parallel(kl, nm, wpp))
+            del wpp
         wu = kmpp_synth.unitsphere(device="cuda")
         res["kmeans_parallel"].append(kmeans_parallel(kl, "unitsphere", wu, reps=1))
         del wu
@@ -587,9 +756,11 @@ def main():
     if not args.no_spaces:
         res["memory_spaces"] = memory_spaces(kl)
     if not args.no_cpu_baseline:
-        Xh = X.cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline(Xh, K)
-        res["cpu_baseline_1core"] = cpu_baseline_1core(Xh)
+        _log("cpu baseline: FP64 oracle on the host cores")
+        res["cpu_baseline"] = cpu_baseline(Xh, K, C_h)
+        _log(f"  {res['cpu_baseline']['sample']}")
+        res["cpu_baseline_1core"] = cpu_baseline(Xh, K, C_h, passes=8, rows=4096, nthreads=1)
+        _log(f"  {res['cpu_baseline_1core']['sample']}")
     print(json.dumps(res), flush=True)
 
 

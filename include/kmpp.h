@@ -287,7 +287,10 @@ typedef struct kmpp_instance {
  * kmpp_seed_batched_launch:  enqueues only kernel launches and so may be
  *              captured into a graph and replayed;
  * kmpp_seed_batched:         prepare + launch.
- * Status: KMPP_E_TIMEOUT if a gang barrier wait expired (results undefined).
+ * Status: KMPP_W_DEGENERATE or KMPP_E_NONFINITE as for kmpp_seed (for the
+ * whole batch: some instance met the condition), KMPP_E_TIMEOUT if a gang
+ * barrier wait expired (results undefined; the budget scales with the plan's
+ * estimated length, see kmpp_tune_load).
  */
 size_t kmpp_batched_workspace_bytes(const kmpp_instance* inst, int32_t n_inst);
 int kmpp_seed_batched_prepare(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, void* workspace,
@@ -317,8 +320,11 @@ int kmpp_graph_destroy(kmpp_graph g);
  * override the built-in choices for the seed pass (draw: KMPP_DRAW_PASS or
  * KMPP_DRAW_KERNEL); lines
  * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
- * alpha) set the batched planner's cost model.  Returns the number of
- * entries read or KMPP_E_INVALID. */
+ * alpha) set the batched planner's cost model; "batched wait_ms <v>" sets
+ * the budget of one gang wait (v < 0: automatic, eight times the plan's
+ * estimated length and at least one second; 0: every wait gives up at once,
+ * which forces KMPP_E_TIMEOUT for testing).  Returns the number of entries
+ * read or KMPP_E_INVALID. */
 int kmpp_tune_load(const char* path);
 
 /*

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkmpp.so")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
@@ -23,19 +23,17 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def _compile_all(verbose):
     odir = os.path.join(HERE, "_build")
     os.makedirs(odir, exist_ok=True)
-    procs = []
+    procs, objs = [], {}
     for src in sources():
         obj = os.path.join(odir, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *[f for f in FLAGS if f != "-shared"], "-c", "-I", os.path.join(ROOT, "include"),
-               "-I", CSRC, "-o", obj, src]
+        cmd = ["hipcc", *FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", obj, src]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
+        objs[os.path.basename(src)] = obj
     failed = []
     for src, pr in procs:
         out, _ = pr.communicate()
@@ -48,8 +46,14 @@ def build(verbose: bool = False) -> str:
         for src, txt in failed:
             sys.stderr.write(f"---- {src}\n{txt}\n")
         raise RuntimeError("hipcc failed for: " + ", ".join(os.path.basename(s) for s, _ in failed))
+    return objs
+
+
+def build(verbose: bool = False) -> str:
+    objs = _compile_all(verbose)
+    main = [o for name, o in sorted(objs.items())]
     tmp = LIB + ".tmp"
-    subprocess.run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs], check=True)
+    subprocess.run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *main], check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -47,6 +47,7 @@ struct AssignParams {
   float* Ct;            // [d, Kq] the centres transposed (zero past K)
   int32_t Kq;           // K rounded up to 64
   int32_t* cflags;      // [N] the rows queued for the recheck (nflag of them)
+  int32_t* qa;          // [N] BF16/FP8 rows: the rows the first stage queued for the second (nqueue)
 };
 
 // ---- per-format row fragment handling
@@ -79,6 +80,30 @@ __device__ __forceinline__ void top2_merge(float& s1, int& i1, float& s2, float 
     i1 = j1;
   } else {
     s2 = fminf(s2, t1);
+  }
+}
+
+// max(a, b, c, d) in two VALU operations (gfx950's three-input IEEE
+// maximum; a NaN operand makes the result NaN, which the callers' compares
+// then pass over).  No operand is canonicalised first, which the
+// compiler's fmaxf would do to every MFMA result.
+__device__ __forceinline__ float max4(float a, float b, float c, float d) {
+  return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), __builtin_elementwise_maximum(c, d));
+}
+
+// Value e of a lane's quarter of a row from its MFMA fragments (FP32: one
+// value per step; BF16 / FP8 as BF16: eight per step), exact in FP32.
+template <int FMT, int S>
+__device__ __forceinline__ float frag_value(const typename Frag<FMT>::A (&a)[S], int e) {
+  if constexpr (FMT == FMT_F32) {
+    return a[e];
+  } else {
+    // through the fragment's four 32-bit words (element 2w in the low half
+    // of word w, 2w + 1 in the high half), as decode() reads them
+    const uint4 w = __builtin_bit_cast(uint4, a[e / 8]);
+    const int t = e % 8;
+    const uint32_t word = (t >> 1) == 0 ? w.x : (t >> 1) == 1 ? w.y : (t >> 1) == 2 ? w.z : w.w;
+    return (t & 1) ? bf16_hi(word) : bf16_lo(word);
   }
 }
 
@@ -148,16 +173,20 @@ __device__ uint32_t prep_part(const AssignParams& p, int fmt, I tid, I stride) {
   const int DQ = p.dp / 4;
   uint32_t mx = 0u;
   for (I j = tid; j < p.Kp; j += stride) {
-    float a = 0.0f;  // sum over k in order
+    // ||c||^2 summed over k in order in FP64 and rounded once, so each chain
+    // start carries a single FP32 rounding (at most 2^-25 ||c||^2), which the
+    // error bound's slack covers; an FP32 sum would add up to d 2^-24 ||c||^2
+    double a = 0.0;
     for (int k0 = 0; k0 < p.d; k0 += kPrepU) {
       float c[kPrepU];
 #pragma unroll
       for (int u = 0; u < kPrepU; ++u) c[u] = c_at(p, j, k0 + u);
 #pragma unroll
-      for (int u = 0; u < kPrepU; ++u) a = fmaf(c[u], c[u], a);  // +0 past d: a unchanged
+      for (int u = 0; u < kPrepU; ++u) a = fma((double)c[u], (double)c[u], a);  // +0 past d: a unchanged
     }
-    p.cn[j] = j < p.K ? -0.5f * a : -INFINITY;  // exact scaling
-    if (j < p.K) mx = max(mx, __float_as_uint(a));
+    const float af = (float)a;
+    p.cn[j] = j < p.K ? -0.5f * af : -INFINITY;  // exact scaling
+    if (j < p.K) mx = max(mx, __float_as_uint(af));
   }
   if (fmt == FMT_F32) {
     float* Cp = (float*)const_cast<void*>(p.Cp);
@@ -216,18 +245,33 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
 // t = <x, c_j> - ||c_j||^2 / 2 = -score / 2 and the per-pair work is the
 // top-2 update alone (largest t, ties to the smaller index).
 // Waves per SIMD the compiler must allow: FP32 rows of width 97..128 fit 128
-// registers, so four waves (measured faster than three); no constraint otherwise.
-constexpr int assign_min_waves(int fmt, int dqk) { return fmt == FMT_F32 && dqk == 32 ? 4 : 1; }
+// registers, so four waves (measured faster than three); BF16 / FP8 rows of
+// width 65..128 three (the tail's candidate rescoring would otherwise take
+// the registers of a third wave); no constraint otherwise.
+constexpr int assign_min_waves(int fmt, int dqk) {
+  return fmt == FMT_F32 && dqk == 32 ? 4 : (fmt != FMT_F32 && dqk == 4 ? 3 : 1);
+}
 
-template <int FMT, int DQK, int RB>
+//
+// BF16 / FP8 rows run in two stages (NP, the centre parts taken):
+//   NP = 1: every row, products with the centres' BF16 high parts only (half
+//           the matrix work); the bound adds the high part's rounding, at
+//           most 2^-9 |x_k c_k| per term; rows not decided go to queue qa;
+//   NP = 2: only the rows in qa (gathered), products with both parts, the
+//           tight bound; rows not decided go to the recheck queue.
+// FP32 rows take one stage (NP = 1, the FP32 product, tight bound).
+template <int FMT, int DQK, int RB, int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(assign_min_waves(FMT, DQK))))
 void assign_mfma_kernel(AssignParams p) {
   using F = Frag<FMT>;
   constexpr bool BF = FMT != FMT_F32;
-  constexpr int S = DQK;                                 // MFMA steps per centre tile (per product)
-  constexpr int TB = BF ? 2 * S * 64 * 16 : S * 64 * 4;  // bytes of one packed centre tile
-  constexpr int TPC = TB >= 16384 ? 1 : 16384 / TB;      // tiles per chunk
-  constexpr int CHB = TPC * TB;                          // bytes per chunk
+  constexpr bool GATHER = BF && NP == 2;  // rows from qa
+  constexpr bool FIRST = BF && NP == 1;   // undecided rows go to qa
+  constexpr int S = DQK;                                  // MFMA steps per centre tile (per product)
+  constexpr int TBG = BF ? 2 * S * 64 * 16 : S * 64 * 4;  // bytes of one packed centre tile (both parts)
+  constexpr int TB = BF ? NP * S * 64 * 16 : TBG;         // bytes of the parts this stage stages in LDS
+  constexpr int TPC = TB >= 16384 ? 1 : 16384 / TB;       // tiles per chunk
+  constexpr int CHB = TPC * TB;                           // bytes per chunk
   constexpr int LPT = CHB / (256 * 16);                  // 16-byte loads per thread per chunk
   static_assert(CHB % (256 * 16) == 0, "chunk is a whole number of 16-byte loads per thread");
   const int tid = threadIdx.x;
@@ -242,8 +286,18 @@ void assign_mfma_kernel(AssignParams p) {
   __shared__ int s_base;             // where they go in the queue
 
   // first 16-row block of this wave; waves past the last block compute on
-  // clamped rows and store nothing (they still take part in the barriers)
+  // clamped rows and store nothing (they still take part in the barriers).
+  // The second stage's rows are the first stage's queue; workgroups past it
+  // leave at once.
+  const int64_t nrows = GATHER ? (int64_t)p.ctl->nqueue : p.N;
+  if (GATHER && (int64_t)blockIdx.x * 4 * RB * 16 >= nrows) return;
   const int64_t blk0 = ((int64_t)blockIdx.x * 4 + wave) * RB;
+  int32_t rowv[RB];  // the row of each block for this lane's column, -1 past the end
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int64_t i = (blk0 + rb) * 16 + col;
+    rowv[rb] = i < nrows ? (GATHER ? p.qa[i] : (int32_t)i) : -1;
+  }
 
   // ---- row fragments (registers for the whole centre loop) and ||x||^2.
   // A lane's fragment values are consecutive in the row, so rows whose
@@ -254,9 +308,8 @@ void assign_mfma_kernel(AssignParams p) {
   const gptr<const char> xb = as_global(static_cast<const char*>(p.X));
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    int64_t row = (blk0 + rb) * 16 + col;
-    const bool ok = row < p.N;
-    row = ok ? row : p.N - 1;
+    const bool ok = rowv[rb] >= 0;
+    const int64_t row = ok ? rowv[rb] : p.N - 1;
     float acc = 0.0f;
     if constexpr (FMT == FMT_F32) {
       if (S % 4 == 0 && (p.d & 3) == 0) {
@@ -330,28 +383,33 @@ void assign_mfma_kernel(AssignParams p) {
     xs[rb] = acc;
   }
 
-  // ---- running top-2 of t per row block (this lane's centres)
+  // ---- per row block (this lane's centres): the largest t so far (m1),
+  // the tile holding it (tb), and the largest t outside that tile's four
+  // values of this lane (m2)
   float m1[RB], m2[RB];
-  int i1[RB];
+  int tb[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     m1[rb] = -INFINITY;
     m2[rb] = -INFINITY;
-    i1[rb] = INT_MAX;
+    tb[rb] = -1;
   }
 
   // ---- centre chunks through LDS
   const int nch = (Kt + TPC - 1) / TPC;
   const gptr<const char> cp = as_global(static_cast<const char*>(p.Cp));
   const gptr<const char> cnb = as_global(reinterpret_cast<const char*>(p.cn));
-  const int64_t cp_n = (int64_t)Kt * (TB / 16);  // 16-byte words of packed centres
   uint4 pre[LPT];
   uint4 pcn = make_uint4(0u, 0u, 0u, 0u);
+  // chunk c's word w: tile c * TPC + w / (TB / 16), the first TB bytes of the
+  // tile's TBG (the high parts alone come first in each packed tile)
   auto gload = [&](int c) {
 #pragma unroll
     for (int i = 0; i < LPT; ++i) {
-      const int64_t idx = (int64_t)c * (CHB / 16) + i * 256 + tid;
-      pre[i] = idx < cp_n ? load_raw<16>(cp + idx * 16) : make_uint4(0u, 0u, 0u, 0u);
+      const int w = i * 256 + tid;
+      const int64_t tile = (int64_t)c * TPC + w / (TB / 16);
+      const int64_t idx = tile * (TBG / 16) + w % (TB / 16);
+      pre[i] = tile < Kt ? load_raw<16>(cp + idx * 16) : make_uint4(0u, 0u, 0u, 0u);
     }
     const int64_t ci = (int64_t)c * TPC * 4 + tid;  // 16-byte entry of cn
     if (tid < TPC * 4) pcn = ci < (int64_t)Kt * 4 ? load_raw<16>(cnb + ci * 16) : make_uint4(0u, 0u, 0u, 0u);
@@ -383,9 +441,9 @@ void assign_mfma_kernel(AssignParams p) {
             acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv, a[rb][s], s == 0 ? init : acc[rb], 0, 0, 0);
         }
       } else {
-        const uint4* bp = &sbuf[c & 1][(t * 2 * S) * 64 + lane];
+        const uint4* bp = &sbuf[c & 1][(t * NP * S) * 64 + lane];
 #pragma unroll
-        for (int hp = 0; hp < 2; ++hp)
+        for (int hp = 0; hp < NP; ++hp)
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const v8bf cv = __builtin_bit_cast(v8bf, bp[(hp * S + s) * 64]);
@@ -396,22 +454,21 @@ void assign_mfma_kernel(AssignParams p) {
           }
       }
     };
-    // running top-2 update with tile t's values: the new second is the
-    // median of (best, second, value); four VALU operations per value and
-    // no NaN canonicalisation (a NaN value leaves both unchanged: med3 then
-    // returns the smaller of best and second, and no comparison holds)
+    // tile t's four values per row block enter as one: their maximum moves
+    // (m1, tb, m2) -- the new m2 is the median of (m1, m2, tile maximum);
+    // six VALU operations per four values (a NaN value makes the tile
+    // maximum NaN: no compare holds, and med3 then returns the smaller of
+    // m1 and m2, so m1, tb and m2 stay unchanged)
     auto epilogue = [&](int t, const v4f(&acc)[RB]) {
-      const int j0 = (c * TPC + t) * 16 + 4 * q;
+      const int tg = c * TPC + t;
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float tv = acc[rb][v];
-          m2[rb] = __builtin_amdgcn_fmed3f(m1[rb], m2[rb], tv);
-          const bool gt = tv > m1[rb];
-          i1[rb] = gt ? j0 + v : i1[rb];
-          m1[rb] = gt ? tv : m1[rb];
-        }
+      for (int rb = 0; rb < RB; ++rb) {
+        const float tmax = max4(acc[rb][0], acc[rb][1], acc[rb][2], acc[rb][3]);
+        m2[rb] = __builtin_amdgcn_fmed3f(m1[rb], m2[rb], tmax);
+        const bool gt = tmax > m1[rb];
+        tb[rb] = gt ? tg : tb[rb];
+        m1[rb] = gt ? tmax : m1[rb];
+      }
     };
     for (int t = 0; t < tn; ++t) {
       v4f acc[RB];
@@ -422,69 +479,97 @@ void assign_mfma_kernel(AssignParams p) {
     __syncthreads();
   }
 
-  // ---- scores s = -2 t (exact), merged over the four lane groups of a row
-  float s1[RB], s2[RB];
+  // ---- merged over the four lane groups of a row (lanes col + 16 q): the
+  // group with the largest m1 (ties: the smaller centre index) gives the
+  // candidates, its four centres of tile tb; every other value of the row
+  // is at most `out` (its m2, the other groups' m1)
+  float b1[RB], out[RB];
+  int bj[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    s1[rb] = -2.0f * m1[rb];
-    s2[rb] = -2.0f * m2[rb];
+    b1[rb] = m1[rb];
+    out[rb] = m2[rb];
+    bj[rb] = tb[rb] >= 0 ? tb[rb] * 16 + 4 * q : INT_MAX;
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
-      const float t1 = __shfl_xor(s1[rb], o, 64);
-      const int j1 = __shfl_xor(i1[rb], o, 64);
-      const float t2 = __shfl_xor(s2[rb], o, 64);
-      top2_merge(s1[rb], i1[rb], s2[rb], t1, j1, t2);
+      const float o1 = __shfl_xor(b1[rb], o, 64);
+      const int oj = __shfl_xor(bj[rb], o, 64);
+      const float oo = __shfl_xor(out[rb], o, 64);
+      if (o1 > b1[rb] || (o1 == b1[rb] && oj < bj[rb])) {
+        out[rb] = fmaxf(b1[rb], oo);
+        b1[rb] = o1;
+        bj[rb] = oj;
+      } else {
+        out[rb] = fmaxf(out[rb], o1);
+      }
     }
   }
 
-  // ---- per row (lanes of a row: same col, q = 0..3): ||x||, bound, direct
-  // distance to the best centre over this lane's quarter
+  // ---- per row: ||x||, the bound, and the direct FP32 distances to the
+  // four candidates over this lane's quarter of the row (the row values are
+  // the fragments already in registers, exact), summed over the four lane
+  // groups; the nearest candidate (ties: the smaller index) is the label
   const float cmax2 = *p.cmax2;
   const float cmax = sqrtf(cmax2);
   constexpr float kGrowth = 1.05f;
+  constexpr int QV = F::VPL * S;  // values per lane quarter (= DQ)
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     float x2 = xs[rb];
     x2 += __shfl_xor(x2, 16, 64);
     x2 += __shfl_xor(x2, 32, 64);
-    const int64_t row = (blk0 + rb) * 16 + col;
-    const int best = i1[rb];
-    const float gap = s2[rb] - s1[rb];
+    const int64_t row = rowv[rb];
+    // t values: the score gap is twice the t gap
+    const float gap = 2.0f * (b1[rb] - out[rb]);
     const float xn = sqrtf(x2) * 1.0001f;
     const float mag = cmax2 + 2.0f * xn * cmax;
-    const float unit =
-        (FMT == FMT_F32) ? (float)(p.dp + 8) * 0x1p-24f : (float)(2 * p.dp + 8) * 0x1p-24f + 0x1p-16f;
-    const float E = unit * mag * kGrowth;
-    const bool sure = gap > 2.0f * E && best < p.K;
-    // direct distance to the best centre over this lane's quarter: the
-    // row values are the fragments already in registers (exact), the
-    // centre's slice is read with all loads in flight
-    float dd = 0.0f;
-    const int bj = best < p.K ? best : 0;
-    const float* crow = p.C + (int64_t)bj * p.d;
-    constexpr int QV = F::VPL * S;  // values per lane quarter (= DQ)
-    float cv[QV];
+    // score error bound: FP32 accumulation over the products and the chain
+    // start, plus (BF16 / FP8, NP = 2) the remainder part's rounding 2^-17
+    // |x||c| or (NP = 1) the high part's rounding 2^-9 |x||c|, doubled
+    const float unit = (FMT == FMT_F32 || NP == 1) ? (float)(p.dp + 8) * 0x1p-24f
+                                                   : (float)(2 * p.dp + 8) * 0x1p-24f + 0x1p-16f;
+    float E = unit * mag * kGrowth;
+    if constexpr (FIRST) E += 0x1p-8f * xn * cmax * kGrowth;
+    const bool sure = gap > 2.0f * E && bj[rb] < p.K;
+    // one candidate at a time (few registers: the tail must not lower the
+    // main loop's occupancy); a lane's quarter of a candidate row is
+    // contiguous, read with 16-byte loads where it lies wholly inside the
+    // row, else element by element (index clamped, positions past d masked)
+    float dbest = INFINITY;
+    int best = INT_MAX;
+    for (int v = 0; v < 4; ++v) {
+      const int j = bj[rb] < p.K ? bj[rb] + v : 0;
+      const float* crow = p.C + (int64_t)min(j, p.K - 1) * p.d;
+      float dd = 0.0f;
+      if (QV % 4 == 0 && (p.d & 3) == 0 && (q + 1) * QV <= p.d) {
+        const float4* c4 = reinterpret_cast<const float4*>(crow + q * QV);
 #pragma unroll
-    for (int e = 0; e < QV; ++e) {
-      const int k = q * QV + e;
-      cv[e] = k < p.d ? crow[k] : 0.0f;
-    }
-    float xq[QV];
+        for (int i = 0; i < QV / 4; ++i) {
+          const float4 cc = c4[i];
+          const float cw[4] = {cc.x, cc.y, cc.z, cc.w};
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if constexpr (FMT == FMT_F32)
-        xq[s] = a[rb][s];
-      else
-        decode<FMT_BF16, 16>(__builtin_bit_cast(uint4, a[rb][s]), xq + 8 * s);
-    }
+          for (int e = 0; e < 4; ++e) {
+            const float df = frag_value<FMT>(a[rb], 4 * i + e) - cw[e];
+            dd = fmaf(df, df, dd);
+          }
+        }
+      } else {
 #pragma unroll
-    for (int e = 0; e < QV; ++e) {
-      const float df = xq[e] - cv[e];
-      dd = (q * QV + e < p.d) ? fmaf(df, df, dd) : dd;
+        for (int e = 0; e < QV; ++e) {
+          const int k = q * QV + e;
+          const float df = frag_value<FMT>(a[rb], e) - crow[min(k, p.d - 1)];
+          dd = k < p.d ? fmaf(df, df, dd) : dd;
+        }
+      }
+      dd += __shfl_xor(dd, 16, 64);
+      dd += __shfl_xor(dd, 32, 64);
+      if (j < p.K && bj[rb] < p.K && dd < dbest) {
+        dbest = dd;
+        best = j;
+      }
     }
-    dd += __shfl_xor(dd, 16, 64);
-    dd += __shfl_xor(dd, 32, 64);
-    const bool mine = q == 0 && row < p.N;
+    const float dd = dbest;
+    const bool mine = q == 0 && row >= 0;
     if (mine && sure) {
       p.labels[row] = best;
       if (p.mind) p.mind[row] = dd;
@@ -503,9 +588,11 @@ void assign_mfma_kernel(AssignParams p) {
   // workgroup (the queue's order does not matter: each row's recheck is
   // independent of the others)
   __syncthreads();
-  if (tid == 0) s_base = s_nf ? (int)atomicAdd(&p.ctl->nflag, (uint32_t)s_nf) : 0;
+  uint32_t* const counter = FIRST ? &p.ctl->nqueue : &p.ctl->nflag;
+  int32_t* const queue = FIRST ? p.qa : p.cflags;
+  if (tid == 0) s_base = s_nf ? (int)atomicAdd(counter, (uint32_t)s_nf) : 0;
   __syncthreads();
-  for (int i = tid; i < s_nf; i += 256) p.cflags[s_base + i] = s_q[i];
+  for (int i = tid; i < s_nf; i += 256) queue[s_base + i] = s_q[i];
 }
 
 // ---------------------------------------------------------------- recheck
@@ -656,6 +743,7 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
 __global__ void assign_reset_kernel(Ctl* ctl, float* cmax2) {
   ctl->status = KMPP_OK;
   ctl->nflag = 0u;
+  ctl->nqueue = 0u;
   *cmax2 = 0.0f;
 }
 
@@ -667,6 +755,7 @@ __global__ __launch_bounds__(1024) void assign_setup_kernel(AssignParams p, int 
   if (tid == 0) {
     p.ctl->status = KMPP_OK;
     p.ctl->nflag = 0u;
+    p.ctl->nqueue = 0u;
   }
   // every index fits 32 bits here (Kp * dp <= 65536, d <= 256)
   transpose_part<uint32_t>(p, (uint32_t)tid, 1024u);
@@ -690,7 +779,7 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 constexpr int64_t kSetupOneWg = 1 << 16;
 
 struct AssignLayout {
-  size_t cn, cmax, cp, ct, cflags, total;
+  size_t cn, cmax, cp, ct, cflags, qa, total;
   int Kp, dp, Kq;
 };
 
@@ -721,15 +810,21 @@ AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   off += a256(sizeof(float) * (size_t)L.Kq * (size_t)d);
   L.cflags = off;
   off += a256(sizeof(int32_t) * (size_t)N);
+  L.qa = off;
+  if (dtype != KMPP_F32) off += a256(sizeof(int32_t) * (size_t)N);
   L.total = off;
   return L;
 }
 
+// One stage over all rows (FP32), or the two stages of BF16 / FP8 rows (the
+// second's grid covers every row; its workgroups past the queue leave at once).
 template <int FMT, int DQK, int RB>
 hipError_t launch_main(AssignParams& p, hipStream_t stream) {
   const int64_t waves = (p.nblk + RB - 1) / RB;
   const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((assign_mfma_kernel<FMT, DQK, RB>), dim3((unsigned)blocks), dim3(256), 0, stream, p);
+  hipLaunchKernelGGL((assign_mfma_kernel<FMT, DQK, RB, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p);
+  if constexpr (FMT != FMT_F32)
+    hipLaunchKernelGGL((assign_mfma_kernel<FMT, DQK, RB, 2>), dim3((unsigned)blocks), dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 
@@ -795,6 +890,7 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.Ct = reinterpret_cast<float*>(w + L.ct);
   p.Kq = L.Kq;
   p.cflags = reinterpret_cast<int32_t*>(w + L.cflags);
+  p.qa = reinterpret_cast<int32_t*>(w + L.qa);
 
   p.all_rows = 0;
 

@@ -68,22 +68,32 @@ struct BPlan {
   uint64_t* iflag;       // per instance: (step << 32) | index
   Ctl* ctl;
   uint64_t seed;
+  uint64_t wait_ticks;   // budget of one gang wait in real-time counter ticks; 0: give up at once
   int32_t n_inst, W, n_mslots;
 };
 
 __device__ __forceinline__ uint64_t tag16(int m) { return 0x8000u | ((uint32_t)m & 0x7FFFu); }
 
-// Bounded wait until (*addr & mask) == want (about a second at most).  Once
-// any wait of the launch has expired, later waits return at once, so the
-// grid drains quickly; the results are then undefined and the status says so.
-__device__ __forceinline__ uint64_t wait_for(uint64_t* addr, uint64_t mask, uint64_t want, Ctl* ctl) {
+// Bounded wait until (*addr & mask) == want.  The budget (BPlan.wait_ticks,
+// on the constant-rate real-time counter) is set by the host from the
+// plan's estimated length, so a member that waits for peers still busy with
+// earlier items of their lists is not cut off; 0 makes every wait give up at
+// once (a host-forced expiry, for testing the error path).  Once any wait of
+// the launch has expired, later waits return at once, so the grid drains
+// quickly; the results are then undefined and the status says so.
+__device__ __forceinline__ uint64_t wait_for(uint64_t* addr, uint64_t mask, uint64_t want, const BPlan& P) {
+  if (P.wait_ticks == 0) {
+    raise_status(P.ctl, KMPP_E_TIMEOUT);
+    return want;
+  }
   uint64_t v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   for (uint32_t i = 0; (v & mask) != want; ++i) {
     if ((i & 255) == 255) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (i >= (1u << 20) ||
-          __hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KMPP_E_TIMEOUT) {
-        raise_status(ctl, KMPP_E_TIMEOUT);
+      if (__builtin_amdgcn_s_memrealtime() - t0 > P.wait_ticks ||
+          __hip_atomic_load(&P.ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == KMPP_E_TIMEOUT) {
+        raise_status(P.ctl, KMPP_E_TIMEOUT);
         return want;
       }
     }
@@ -216,7 +226,7 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
       if (wave == 0) {
         double val = 0.0;
         if (lane < w) {
-          const uint64_t bits = wait_for(&P.mslots[I.slot0 + (m & 1) * w + lane], 0xFFFFull, tag16(m), P.ctl);
+          const uint64_t bits = wait_for(&P.mslots[I.slot0 + (m & 1) * w + lane], 0xFFFFull, tag16(m), P);
           val = __longlong_as_double((long long)(bits & ~0xFFFFull));
         }
         // fixed-order wave scan of member totals
@@ -328,7 +338,7 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
       next = S.s_next;
     } else {
       if (tid == 0) {
-        const uint64_t v = wait_for(&P.iflag[b], 0xFFFFFFFF00000000ull, (uint64_t)(m + 1) << 32, P.ctl);
+        const uint64_t v = wait_for(&P.iflag[b], 0xFFFFFFFF00000000ull, (uint64_t)(m + 1) << 32, P);
         S.s_next = (int64_t)(v & 0xFFFFFFFFull);
       }
       __syncthreads();
@@ -396,6 +406,7 @@ struct Tune {
   double sync1_us = 2.5;     // per seed step, gang of one
   double syncw_us = 6.0;     // per seed step, larger gangs
   double alpha = 1.0;        // cap of one instance's time, as a multiple of the mean load
+  double wait_ms = -1.0;     // gang wait budget: < 0 automatic (from the plan), 0 give up at once
 };
 Tune g_tune;
 
@@ -486,6 +497,20 @@ int workgroups() {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel, kBNT, 0) != hipSuccess || occ <= 0) occ = 1;
   return num_cus() * std::min(occ, g_tune.wg_per_cu);
 }
+
+// The budget of one gang wait, in ticks of the device's constant-rate
+// real-time counter: a wait can last as long as the peers' earlier list
+// items, at most the plan's estimated length, so eight times that with a
+// floor of one second (the cost model is an estimate); the tuning table's
+// wait_ms overrides it (0: every wait gives up at once).
+uint64_t wait_budget_ticks(const Tune& T, double makespan_us) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;  // the 100 MHz counter of the Instinct family
+  const double ms = T.wait_ms >= 0.0 ? T.wait_ms : std::max(1000.0, 8.0 * makespan_us * 1e-3);
+  return (uint64_t)(ms * (double)khz);
+}
 }  // namespace
 
 int batched_tune_set(const char* key, double v) {
@@ -494,6 +519,7 @@ int batched_tune_set(const char* key, double v) {
   else if (!strcmp(key, "sync1_us")) g_tune.sync1_us = v;
   else if (!strcmp(key, "syncw_us")) g_tune.syncw_us = v;
   else if (!strcmp(key, "alpha")) g_tune.alpha = v;
+  else if (!strcmp(key, "wait_ms")) g_tune.wait_ms = v;
   else return KMPP_E_INVALID;
   return KMPP_OK;
 }
@@ -556,6 +582,7 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
     H.slot0 = slot0;
     slot0 += 2 * L.gang[b];
   }
+  double makespan_us = 0.0;
   for (int b : order) {
     const int g = L.gang[b];
     std::vector<Slot> got;
@@ -569,6 +596,7 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
       lists[got[k].second].push_back(BItem{b, (int16_t)k, (int16_t)g});
       heap.push({start + tb[b], got[k].second});
     }
+    makespan_us = std::max(makespan_us, start + tb[b]);
   }
   std::vector<BItem> items;
   std::vector<int32_t> begin(W + 1, 0);
@@ -594,6 +622,7 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
   ph.plan.iflag = reinterpret_cast<uint64_t*>(w + L.iflag);
   ph.plan.ctl = reinterpret_cast<Ctl*>(w);
   ph.plan.seed = seed;
+  ph.plan.wait_ticks = wait_budget_ticks(T, makespan_us);
   ph.plan.n_inst = n;
   ph.plan.W = W;
   ph.plan.n_mslots = L.n_mslots;

@@ -26,7 +26,8 @@ struct Ctl {
   int32_t status;      // KMPP_OK, a warning (>0) or an error (<0)
   uint32_t arrive;     // reserved (0)
   uint32_t nflag;      // assignment: rows queued for the direct-form recheck
-  uint32_t pad[61];
+  uint32_t nqueue;     // assignment, BF16/FP8 rows: rows the first stage left to the second
+  uint32_t pad[60];
 };
 static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 

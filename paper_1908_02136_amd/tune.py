@@ -17,6 +17,7 @@ The result is written as text lines
     python -m paper_1908_02136_amd.tune [--quick] [--out PATH]
         [--only DTYPE:D,...]   retune these cases, keep the table's other lines
         [--draw-only]          keep every schedule, re-time only the draw
+        [--batched-only]       retune the batched planner, keep the seed lines
 """
 from __future__ import annotations
 
@@ -109,26 +110,32 @@ def tune_seed(kl, cases, quick, keep=None):
 
 
 def tune_batched(kl, quick):
+    """The planner's knobs for the 512-instance batch: workgroups per CU (the
+    persistent grid), the cap on one instance's time relative to the mean
+    load (sets gang sizes) and the per-seed cost of a gang's exchange (the
+    cost model's gang sync), timed on the whole batch."""
     import kmpp_synth
     spec = kmpp_synth.batched_spec()
     Xs = [kmpp_synth.batched_instance(b, spec.N[b], spec.d[b], spec.K[b], device="cuda") for b in range(512)]
     best = None
     path = os.path.join(HERE, "_tune_tmp.txt")
-    for wpc in (1, 2):
-        for alpha in ((0.5, 1.0, 2.0) if not quick else (1.0,)):
-            with open(path, "w") as f:
-                f.write(f"batched wg_per_cu {wpc}\nbatched alpha {alpha}\n")
-            kl.kmpp_tune_load(path)
-            outs, ws = kl.kmpp_seed_batched_prepare(Xs, spec.K, 0)
-            ms = _time(lambda: kl.kmpp_seed_batched_launch(ws), reps=2)
-            st = kl.kmpp_status(ws)
-            print(f"batched wg_per_cu={wpc} alpha={alpha}: {ms:.2f} ms status {st}", flush=True)
-            if st == 0 and (best is None or ms < best[0]):
-                best = (ms, wpc, alpha)
+    grid = [(w, a, sw) for w in (1, 2, 3, 4) for a in (0.25, 0.5, 1.0, 2.0) for sw in (3.0, 6.0, 12.0)]
+    if quick:
+        grid = [(w, 1.0, 6.0) for w in (1, 2, 3, 4)]
+    for wpc, alpha, syncw in grid:
+        with open(path, "w") as f:
+            f.write(f"batched wg_per_cu {wpc}\nbatched alpha {alpha}\nbatched syncw_us {syncw}\n")
+        kl.kmpp_tune_load(path)
+        outs, ws = kl.kmpp_seed_batched_prepare(Xs, spec.K, 0)
+        ms = _time(lambda: kl.kmpp_seed_batched_launch(ws), reps=2)
+        st = kl.kmpp_status(ws)
+        print(f"batched wg_per_cu={wpc} alpha={alpha} syncw_us={syncw}: {ms:.2f} ms status {st}", flush=True)
+        if st == 0 and (best is None or ms < best[0]):
+            best = (ms, wpc, alpha, syncw)
     os.remove(path)
     if best is None:
         return []
-    return [f"batched wg_per_cu {best[1]}", f"batched alpha {best[2]}"]
+    return [f"batched wg_per_cu {best[1]}", f"batched alpha {best[2]}", f"batched syncw_us {best[3]}"]
 
 
 def main():
@@ -137,6 +144,7 @@ def main():
     ap.add_argument("--out", default=os.path.join(HERE, "tune_table.txt"))
     ap.add_argument("--only", default="", help="comma list of DTYPE:D cases to retune")
     ap.add_argument("--draw-only", action="store_true")
+    ap.add_argument("--batched-only", action="store_true", help="retune the batched planner, keep the seed lines")
     args = ap.parse_args()
     import paper_1908_02136_amd as kl
     kl.lib()
@@ -155,7 +163,10 @@ def main():
             elif f and f[0] == "batched":
                 other.append(ln.strip())
     lines = ["# written by paper_1908_02136_amd/tune.py on " + torch.cuda.get_device_name(0)]
-    if args.only or args.draw_only:
+    if args.batched_only:
+        kept = [ln.strip() for ln in open(args.out) if ln.startswith("seed ")] if os.path.exists(args.out) else []
+        lines += kept + tune_batched(kl, args.quick)
+    elif args.only or args.draw_only:
         only = {tuple(int(x) for x in c.split(":")) for c in args.only.split(",") if c}
         keep = {k: v for k, v in old.items() if k not in only}
         lines += tune_seed(kl, [c for c in cases if (c[0], c[1]) in only or (c[0], c[1]) in keep], args.quick,

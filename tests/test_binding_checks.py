@@ -106,3 +106,4 @@ def test_batched_rejections(kl):
         kl.kmpp_seed_batched(Xs, [4, 4], outs=bad)
     with pytest.raises(ValueError, match="at least one"):
         kl.kmpp_seed_batched([], [])
+

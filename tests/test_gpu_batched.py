@@ -136,3 +136,51 @@ def test_rejects_bad_instances(kl):
     X = torch.zeros((10, 4), device="cuda")
     with pytest.raises(kl.KmppError):
         kl.kmpp_seed_batched([X], [11])         # K > N
+
+
+def _gang_batch():
+    # one instance large enough for a gang of workgroups, among small ones
+    return [(200_000, 64, 64), (150_000, 16, 64)] + [(3_000, 8, 20)] * 6
+
+
+def test_degenerate_instance_warns(kl):
+    # an instance with fewer distinct rows than seeds: the batch's status is
+    # the warning, and every instance still matches the oracle (uniform
+    # draws once the sum of D is zero)
+    specs = _gang_batch()
+    Xs, Ks = _batch(specs, seed=7)
+    Xs[3] = torch.ones((3_000, 8), device="cuda")
+    outs, ws = kl.kmpp_seed_batched(Xs, Ks, 2)
+    assert kl.kmpp_status(ws) == kl.W_DEGENERATE
+    _check_all(Xs, Ks, outs, 2)
+
+
+def test_nonfinite_instance_errors(kl):
+    specs = _gang_batch()
+    Xs, Ks = _batch(specs, seed=8)
+    Xs[5][17, 3] = float("nan")
+    outs, ws = kl.kmpp_seed_batched(Xs, Ks, 2)
+    assert kl.kmpp_status(ws) == kl.E_NONFINITE
+    # the other instances are unaffected
+    _check_all(Xs, Ks, outs, 2, which=[0, 1, 2, 3, 4, 6, 7])
+
+
+def test_forced_wait_expiry_reports_timeout(kl, tmp_path):
+    # the host sets a zero wait budget: every gang wait gives up at once, so
+    # the launch drains normally and reports KMPP_E_TIMEOUT; the automatic
+    # budget is restored afterwards and the same batch is correct again
+    specs = _gang_batch()
+    Xs, Ks = _batch(specs, seed=9)
+    t0 = tmp_path / "wait0.txt"
+    t0.write_text("batched wait_ms 0\n")
+    t1 = tmp_path / "wait_auto.txt"
+    t1.write_text("batched wait_ms -1\n")
+    try:
+        assert kl.kmpp_tune_load(str(t0)) == 1
+        outs, ws = kl.kmpp_seed_batched(Xs, Ks, 4)
+        assert kl.kmpp_status(ws) == kl.E_TIMEOUT
+    finally:
+        assert kl.kmpp_tune_load(str(t1)) == 1
+    outs, ws = kl.kmpp_seed_batched(Xs, Ks, 4)
+    assert kl.kmpp_status(ws) == 0
+    _check_all(Xs, Ks, outs, 4)
