@@ -30,7 +30,8 @@
  *     is enqueued;
  *   - the caller owns every buffer, including the workspace, whose size the
  *     matching *_workspace_bytes function gives; the library allocates no
- *     device memory in any entry point;
+ *     device memory in any entry point (kmpp_seed_noalloc uses a fixed
+ *     device array of the library instead of a workspace);
  *   - work is enqueued without synchronising, except kmpp_status,
  *     kmpp_seed_batched_prepare and kmpp_seed_parallel (stated below);
  *   - arguments are validated before anything is enqueued: a negative
@@ -66,7 +67,8 @@ enum {
   KMPP_E_HIP = -3,          /* a HIP runtime call failed */
   KMPP_E_NONFINITE = -4,    /* sum(D) not finite (NaN or Inf in X) */
   KMPP_E_UNSUPPORTED = -5,  /* shape or format not supported */
-  KMPP_E_TIMEOUT = -6       /* a bounded device-side wait expired */
+  KMPP_E_TIMEOUT = -6,      /* a bounded device-side wait expired */
+  KMPP_E_TOO_LARGE = -7     /* input beyond the fixed scratch of kmpp_seed_noalloc */
 };
 
 #define KMPP_MAX_D 4096
@@ -161,6 +163,31 @@ size_t kmpp_seed_workspace_bytes(int64_t N, int32_t d, int32_t K, int32_t dtype)
 int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, float* out_centers,
               float* out_D, int64_t* out_idx, const void* Xq, const int8_t* Xq_exp, int32_t dtype,
               const kmpp_seed_opts* opts, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * kmpp_seed without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Exported by libkmpp_noalloc.so (linked to
+ * libkmpp.so), so that only its callers load its fixed device array.
+ * Same arguments, results and launches as kmpp_seed (bit-identical seeds,
+ * centres and D), except:
+ *   - the workspace is a fixed device array inside the library (about
+ *     16 MiB per device, held by every device the library runs on until the
+ *     process ends), so N <= KMPP_NOALLOC_MAX_N, else KMPP_E_TOO_LARGE and
+ *     nothing is launched; the entry point allocates nothing;
+ *   - out_status: device int32 [1] or NULL, receives the status word
+ *     (KMPP_OK, KMPP_W_DEGENERATE or KMPP_E_NONFINITE) from the last pass;
+ *     kmpp_status does not apply;
+ *   - `stream` must belong to the current device (the array used is the
+ *     current device's);
+ *   - every call on one device shares that device's array: calls that may
+ *     overlap on one device (other streams, other threads) race and give
+ *     undefined results; order them on one stream.
+ */
+#define KMPP_NOALLOC_MAX_N 1048576
+int kmpp_seed_noalloc(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, float* out_centers,
+                      float* out_D, int64_t* out_idx, const void* Xq, const int8_t* Xq_exp, int32_t dtype,
+                      const kmpp_seed_opts* opts, int32_t* out_status, void* stream);
 
 /*
  * Nearest-seed assignment: the partition O of the paper's Algorithm 1.

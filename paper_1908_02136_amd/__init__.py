@@ -17,6 +17,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkmpp.so")
+# kmpp_seed_noalloc lives in a library of its own (linked to libkmpp.so): its
+# fixed device array is loaded only by the callers of that entry point
+LIB_NOALLOC_PATH = os.path.join(HERE, "libkmpp_noalloc.so")
 TUNE_PATH = os.path.join(HERE, "tune_table.txt")
 
 KMPP_F32, KMPP_BF16, KMPP_FP8_E4M3 = 0, 1, 2
@@ -27,11 +30,14 @@ ROW_PATHS = {"cached": KMPP_ROWS_CACHED, "nontemporal": KMPP_ROWS_NONTEMPORAL, "
 CENTRE_SOURCES = {"lds": KMPP_CENTRE_LDS, "scalar": KMPP_CENTRE_SCALAR, "global": KMPP_CENTRE_GLOBAL}
 KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL = 0, 1, 2
 OK, W_DEGENERATE = 0, 1
-E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT = -1, -2, -3, -4, -5, -6
+E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT, E_TOO_LARGE = -1, -2, -3, -4, -5, -6, -7
 MAX_D = 4096
+NOALLOC_MAX_N = 1 << 20
 
-# Every symbol the header declares (checked by the test suite).
-SYMBOLS = [
+# Every symbol the header declares (checked by the test suite); the last
+# list's are exported by libkmpp_noalloc.so, the others by libkmpp.so.
+NOALLOC_SYMBOLS = ["kmpp_seed_noalloc"]
+SYMBOLS = NOALLOC_SYMBOLS + [
     "kmpp_seed_workspace_bytes", "kmpp_seed", "kmpp_assign_workspace_bytes", "kmpp_assign", "kmpp_quantize",
     "kmpp_lloyd_workspace_bytes", "kmpp_lloyd", "kmpp_seed_parallel_capacity",
     "kmpp_seed_parallel_workspace_bytes", "kmpp_seed_parallel",
@@ -122,6 +128,25 @@ def lib() -> ctypes.CDLL:
     if os.path.exists(TUNE_PATH):
         L.kmpp_tune_load(TUNE_PATH.encode())
     _lib = L
+    return L
+
+
+_lib_noalloc = None
+
+
+def lib_noalloc() -> ctypes.CDLL:
+    """Load libkmpp_noalloc.so (after libkmpp.so, which it links to)."""
+    global _lib_noalloc
+    if _lib_noalloc is not None:
+        return _lib_noalloc
+    lib()
+    if not os.path.exists(LIB_NOALLOC_PATH):
+        raise RuntimeError(f"{LIB_NOALLOC_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_NOALLOC_PATH)
+    P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    L.kmpp_seed_noalloc.argtypes = [P, i64, i32, i32, u64, P, P, P, P, P, i32, ctypes.POINTER(SeedOpts), P, P]
+    L.kmpp_seed_noalloc.restype = ctypes.c_int
+    _lib_noalloc = L
     return L
 
 
@@ -254,6 +279,32 @@ def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D
                          _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "kmpp_seed")
     return out_idx, out_centers, out_D, ws
+
+
+def kmpp_seed_noalloc(X: torch.Tensor, K: int, seed: int = 0, *, out_centers, out_D=None, out_idx=None,
+                      out_status=None, Xq=None, Xq_exp=None, dtype: int = KMPP_F32, instance: int = 0,
+                      draw: int = KMPP_DRAW_AUTO, stream=None):
+    """kmpp_seed without a workspace (the library's fixed device array;
+    N <= NOALLOC_MAX_N).  Nothing is allocated here either: the caller
+    passes every output (``out_status``: int32 [1] or None)."""
+    N, d = _rows(X)
+    _expect(X, "X", dtype=torch.float32)
+    _check_dtype(dtype)
+    if dtype != KMPP_F32:
+        _expect(Xq, "Xq", itemsize=_ELEM_BYTES[dtype])
+        _expect(Xq, "Xq", shape=(N, d))
+        if dtype == KMPP_FP8_E4M3:
+            _expect(Xq_exp, "Xq_exp", dtype=torch.int8, numel=N)
+    _expect(out_centers, "out_centers", dtype=torch.float32, numel=K * d)
+    _expect(out_D, "out_D", dtype=torch.float32, numel=N, required=False)
+    _expect(out_idx, "out_idx", dtype=torch.int64, numel=K, required=False)
+    _expect(out_status, "out_status", dtype=torch.int32, numel=1, required=False)
+    _require_cuda(X, Xq, Xq_exp, out_centers, out_D, out_idx, out_status)
+    opts = SeedOpts(instance, 0, 0, 0, -1, None, None, 0, draw, None)
+    rc = lib_noalloc().kmpp_seed_noalloc(_ptr(X), N, d, K, seed, _ptr(out_centers), _ptr(out_D), _ptr(out_idx), _ptr(Xq),
+                                 _ptr(Xq_exp), dtype, ctypes.byref(opts), _ptr(out_status), _stream(stream))
+    _check(rc, "kmpp_seed_noalloc")
+    return out_idx, out_centers, out_D
 
 
 def kmpp_status(ws: torch.Tensor, stream=None) -> int:

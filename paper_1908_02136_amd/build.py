@@ -1,4 +1,11 @@
-"""Build libkmpp.so (all HIP sources, gfx950) in-tree with hipcc."""
+"""Build the HIP libraries (gfx950) in-tree with hipcc:
+
+  libkmpp.so          every source in csrc/ but noalloc.hip
+  libkmpp_noalloc.so  noalloc.hip (kmpp_seed_noalloc and its fixed device
+                      array), linked to libkmpp.so; kept apart so that only
+                      callers of that entry point load the code object with
+                      the array
+"""
 from __future__ import annotations
 
 import glob
@@ -10,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkmpp.so")
+LIB_NOALLOC = os.path.join(HERE, "libkmpp_noalloc.so")
+NOALLOC_SRC = "noalloc.hip"
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -51,10 +60,14 @@ def _compile_all(verbose):
 
 def build(verbose: bool = False) -> str:
     objs = _compile_all(verbose)
-    main = [o for name, o in sorted(objs.items())]
+    main = [o for name, o in sorted(objs.items()) if name != NOALLOC_SRC]
     tmp = LIB + ".tmp"
     subprocess.run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *main], check=True)
     os.replace(tmp, LIB)
+    tmp = LIB_NOALLOC + ".tmp"
+    subprocess.run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, objs[NOALLOC_SRC],
+                    "-L" + HERE, "-l:libkmpp.so", "-Wl,-rpath,$ORIGIN"], check=True)
+    os.replace(tmp, LIB_NOALLOC)
     return LIB
 
 

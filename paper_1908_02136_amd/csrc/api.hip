@@ -117,7 +117,7 @@ size_t seed_workspace(int64_t N, int K) { return seed_layout(N, K).total; }
 int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t inst, uint32_t tag,
              const int32_t* wts, float* out_centers, float* out_D, int64_t* out_idx, const void* Xq,
              const int8_t* Xq_exp, int dtype, const kmpp_seed_opts* opts, void* workspace, size_t ws_bytes,
-             hipStream_t stream) {
+             hipStream_t stream, int32_t* status_out) {
   const SeedLayout L = seed_layout(N, K);
   if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
   const SeedVariant* v = nullptr;
@@ -149,6 +149,7 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   p.wts = wts;
   p.tag = tag;
   p.sumD = opts ? opts->out_sumD : nullptr;
+  p.status_out = status_out;
   // the draw at pass start (unweighted seeding, exact-width passes): every
   // workgroup reads all tile sums, so their number is bounded, and its LDS
   // staging must leave the pass's occupancy alone (160 KiB of LDS per CU,
@@ -400,6 +401,7 @@ const char* kmpp_strerror(int code) {
     case KMPP_E_NONFINITE: return "non-finite sum of distances (NaN or Inf in the points)";
     case KMPP_E_UNSUPPORTED: return "unsupported shape or format";
     case KMPP_E_TIMEOUT: return "a device-side wait expired";
+    case KMPP_E_TOO_LARGE: return "input larger than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

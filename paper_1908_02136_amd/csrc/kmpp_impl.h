@@ -37,6 +37,7 @@ struct SeedParams {
   float* Dw;             // draw at pass start: this pass's D (every row; D holds the previous pass's)
   double* tsum_w;        // draw at pass start: this pass's tile sums (tsum holds the previous pass's)
   double* sumD;          // [K] or null: the FP64 sum of D each draw inverted
+  int32_t* status_out;   // or null: the status word, copied by the last pass
 };
 
 // One compiled seed-pass kernel.
@@ -94,7 +95,7 @@ constexpr SeedLayout seed_layout(int64_t N, int64_t K) {
 int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t inst, uint32_t tag,
              const int32_t* wts, float* out_centers, float* out_D, int64_t* out_idx, const void* Xq,
              const int8_t* Xq_exp, int dtype, const kmpp_seed_opts* opts, void* ws, size_t ws_bytes,
-             hipStream_t stream);
+             hipStream_t stream, int32_t* status_out = nullptr);
 size_t seed_workspace(int64_t N, int K);
 
 // Assignment

@@ -441,6 +441,10 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     cidx = p.pass >= 2 ? draw_at_start<NT>(p, cs) : p.idx[0];
   else
     cidx = p.idx[p.pass - 1];
+  // every draw has raised its status by now (the last one in this
+  // workgroup's own thread 0 with DRAWER, else in an earlier launch)
+  if (p.status_out && p.pass == p.K && blockIdx.x == 0 && tid == 0)
+    *p.status_out = __hip_atomic_load(&p.ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const float* cg = p.X + cidx * (int64_t)d;
   const int64_t prev = (FMT != FMT_F32) ? cidx : -1;
   if constexpr (CS == CEN_SCALAR) {

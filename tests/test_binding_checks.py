@@ -52,6 +52,16 @@ def test_seed_rejections(kl):
         kl.kmpp_seed(X, 4)
 
 
+def test_noalloc_rejections(kl):
+    X = f32(100, 8)
+    with pytest.raises(ValueError, match="out_centers is required"):
+        kl.kmpp_seed_noalloc(X, 4, out_centers=None)
+    with pytest.raises(ValueError, match="out_status"):
+        kl.kmpp_seed_noalloc(X, 4, out_centers=f32(4, 8), out_status=torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError, match="out_D"):
+        kl.kmpp_seed_noalloc(X, 4, out_centers=f32(4, 8), out_D=f32(100, 2))
+
+
 def test_assign_rejections(kl):
     X = f32(100, 8)
     C = f32(5, 8)
@@ -107,3 +117,16 @@ def test_batched_rejections(kl):
     with pytest.raises(ValueError, match="at least one"):
         kl.kmpp_seed_batched([], [])
 
+
+def test_noalloc_c_rejections(kl):
+    # argument checks of the allocation-free entry point, before any HIP call
+    import ctypes
+    L = kl.lib_noalloc()
+    fake = ctypes.c_void_p(1 << 20)
+    big = kl.NOALLOC_MAX_N + 1
+    assert L.kmpp_seed_noalloc(fake, big, 2, 1, 0, fake, None, None, None, None, 0, None, None, None) == \
+        kl.E_TOO_LARGE
+    assert L.kmpp_seed_noalloc(fake, 10, 2, 11, 0, fake, None, None, None, None, 0, None, None, None) == -1
+    assert L.kmpp_seed_noalloc(None, 10, 2, 1, 0, fake, None, None, None, None, 0, None, None, None) == -1
+    assert L.kmpp_seed_noalloc(fake, 10, 2, 1, 0, fake, None, None, None, None, 1, None, None, None) == -1
+    assert kl.strerror(kl.E_TOO_LARGE) != "unknown status"
