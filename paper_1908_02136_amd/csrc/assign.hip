@@ -740,6 +740,120 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
   }
 }
 
+// The recheck for rows of width d <= 128 (the MFMA path's queue): a
+// workgroup takes kTR = 32 queued rows at once.  Their values go to LDS as
+// [k][row]; the centres stream through LDS in tiles of kTC = 32 from the
+// transposed copy Ct (128 contiguous bytes per k), double-buffered (the next
+// tile's loads are in flight while the current one is used).  Thread
+// (wave w, lane l) takes centre l % 32 of each tile and the four rows
+// 8w + 4 (l / 32) .. +3, whose values at one k are a single 16-byte LDS read;
+// every centre value serves four rows.  Per thread, centres come in index
+// order (strict comparison keeps the smaller index), and the 32 lanes of a
+// half-wave are merged with ties to the smaller index.
+constexpr int kTR = 32, kTC = 32, kTDMax = 128;
+
+template <int FMT>
+__global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams p) {
+  __shared__ float4 xs4[kTDMax * kTR / 4];           // row values, [k][row]
+  __shared__ float4 cs4[2][kTDMax * kTC / 4];        // centre tiles, [k][centre]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cj = lane & 31;                           // centre within the tile
+  const int r0 = wave * 8 + (lane >> 5) * 4;          // first of this thread's four rows
+  const int d = p.d;
+  const int64_t n = p.all_rows ? p.N : (int64_t)p.ctl->nflag;
+  const int64_t groups = (n + kTR - 1) / kTR;
+  const int ntile = (p.K + kTC - 1) / kTC;            // Kq >= ntile * kTC (Kq is a multiple of 64)
+  const int tw = d * (kTC / 4);                       // 16-byte words of one centre tile
+  const gptr<const char> ctb = as_global(reinterpret_cast<const char*>(p.Ct));
+  float* xs = reinterpret_cast<float*>(xs4);
+  // tile t's words: word w = (k, j4) -> Ct[k][t * kTC + 4 j4 .. +3]
+  constexpr int kPer = kTDMax * kTC / 4 / 256;        // words per thread at most
+  // every load in bounds (word clamped) and issued unconditionally; only
+  // the words of the tile are stored
+  uint4 pre[kPer];
+  auto tload = [&](int t) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int w = min(i * 256 + tid, tw - 1);
+      const int k = w / (kTC / 4), j4 = w % (kTC / 4);
+      pre[i] = load_raw<16>(ctb + ((int64_t)k * p.Kq + (int64_t)t * kTC + 4 * j4) * 4);
+    }
+  };
+  auto tstore = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int w = i * 256 + tid;
+      if (w < tw) cs4[b][w] = __builtin_bit_cast(float4, pre[i]);
+    }
+  };
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    // rows of the group (a short last group repeats its last row)
+    for (int e = tid; e < d * kTR; e += 256) {
+      const int k = e / kTR, r = e % kTR;
+      const int64_t i = min(g * kTR + r, n - 1);
+      const int64_t row = p.all_rows ? i : (int64_t)p.cflags[i];
+      xs[e] = x_at<FMT>(p, row, k);
+    }
+    tload(0);
+    tstore(0);
+    __syncthreads();
+    float best[4];
+    int bi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      best[r] = INFINITY;
+      bi[r] = INT_MAX;
+    }
+    for (int t = 0; t < ntile; ++t) {
+      if (t + 1 < ntile) tload(t + 1);
+      const float* cs = reinterpret_cast<const float*>(cs4[t & 1]);
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int k = 0; k < d; ++k) {
+        const float c = cs[k * kTC + cj];
+        const float4 x = xs4[(k * kTR + r0) / 4];
+        const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float df = xv[r] - c;
+          acc[r] = fmaf(df, df, acc[r]);
+        }
+      }
+      const int j = t * kTC + cj;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (j < p.K && acc[r] < best[r]) {
+          best[r] = acc[r];
+          bi[r] = j;
+        }
+      if (t + 1 < ntile) tstore((t + 1) & 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float b = best[r];
+      int ib = bi[r];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) {
+        const float tb = __shfl_xor(b, o, 64);
+        const int ti = __shfl_xor(ib, o, 64);
+        if (tb < b || (tb == b && ti < ib)) {
+          b = tb;
+          ib = ti;
+        }
+      }
+      const int64_t i = g * kTR + r0 + r;
+      if (cj == 0 && i < n) {
+        const int64_t row = p.all_rows ? i : (int64_t)p.cflags[i];
+        // no comparable distance (NaN in the row or the centres): label -1
+        p.labels[row] = ib < p.K ? ib : -1;
+        if (p.mind) p.mind[row] = ib < p.K ? b : __builtin_nanf("");
+      }
+    }
+    __syncthreads();  // the next group rewrites the row values
+  }
+}
+
 __global__ void assign_reset_kernel(Ctl* ctl, float* cmax2) {
   ctl->status = KMPP_OK;
   ctl->nflag = 0u;
@@ -831,7 +945,9 @@ hipError_t launch_main(AssignParams& p, hipStream_t stream) {
 template <int FMT>
 void launch_recheck(const AssignParams& p, hipStream_t stream) {
   const unsigned grid = 2048;
-  if (p.d <= kRecheckLdsD)
+  if (p.d <= kTDMax)
+    hipLaunchKernelGGL((assign_recheck_tiled_kernel<FMT>), dim3(grid), dim3(256), 0, stream, p);
+  else if (p.d <= kRecheckLdsD)
     hipLaunchKernelGGL((assign_recheck_kernel<FMT, true>), dim3(grid), dim3(256), 0, stream, p);
   else
     hipLaunchKernelGGL((assign_recheck_kernel<FMT, false>), dim3(grid), dim3(256), 0, stream, p);

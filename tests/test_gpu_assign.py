@@ -151,3 +151,25 @@ def test_nan_row_gets_label_minus_one(kl, d):
     assert lab[123] == -1 and np.isnan(mind[123])
     keep = np.arange(N) != 123
     check_assign(Xh.numpy()[keep], Ch.numpy(), lab[keep], mind[keep])
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_large_norm_centres_near_rows(kl, dtype):
+    # every centre and row sits near one far point (coordinates ~1000), so
+    # ||c||^2 ~ 6.4e7 dwarfs every distance (~1e2): the score form's error
+    # bound must carry the rounding of ||c||^2 and route these rows to the
+    # direct-form recheck; labels must still match the FP64 oracle
+    N, d, K = 20_011, 64, 64
+    base = 1000.0
+    g = torch.Generator().manual_seed(17)
+    Ch = (base + torch.randn((K, d), generator=g)).float()
+    Xh = (base + torch.randn((N, d), generator=g)).float()
+    print("assign large-norm centres", dtype, flush=True)
+    if dtype == 0:
+        lab, mind = run_assign(kl, Xh.cuda(), Ch.cuda())
+        Xd = Xh.numpy()
+    else:
+        q, _ = kl.kmpp_quantize(Xh.cuda(), kl.KMPP_BF16)
+        lab, mind = run_assign(kl, q, Ch.cuda(), dtype=kl.KMPP_BF16)
+        Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
+    check_assign(Xd, Ch.numpy(), lab, mind)
