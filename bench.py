@@ -444,17 +444,21 @@ def form_entry(kl, name, w, tag, reps, X_host=None):
     kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt)
     torch.cuda.synchronize()
     ams = time_events(lambda: kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt), max(reps, 3))
+    # the labels alone (output O; the distances are the seed loop's final D)
+    lms = time_events(lambda: kl.kmpp_assign(Xa, C, X_exp=E, dtype=dt, out_mind=False), max(reps, 3))
     flops = 2.0 * N * K * d
     tf = flops / (ams * 1e-3) / 1e12
+    tfl = flops / (lms * 1e-3) / 1e12
     entry = {"seed_ms": ms, "status": st, "dists_per_s": N * K / (ms * 1e-3),
              "seed_GBps": row_bytes * K / (ms * 1e-3) / 1e9,
              "pass_us": pms * 1e3, "pass_GBps": pgbs, "pass_frac_hbm": pgbs / HBM_PEAK_GBS,
              "assign_ms": ams, "assign_TFLOPs": tf, "assign_peak_TFLOPs": MFMA_PEAK_TFLOPS[tag],
-             "assign_frac_mfma": tf / MFMA_PEAK_TFLOPS[tag], "quantize_ms": qms,
+             "assign_frac_mfma": tf / MFMA_PEAK_TFLOPS[tag], "assign_labels_ms": lms,
+             "assign_labels_TFLOPs": tfl, "assign_labels_frac_mfma": tfl / MFMA_PEAK_TFLOPS[tag], "quantize_ms": qms,
              "phi_seed0": float(D.double().sum().item())}
     _log(f"  {name} {tag}: seed {ms:.1f} ms ({entry['dists_per_s']:.3g} dists/s), pass {pms*1e3:.1f} us "
          f"{pgbs:.0f} GB/s, assign {ams:.2f} ms {tf:.1f} TF/s ({entry['assign_frac_mfma']:.3f} of "
-         f"{MFMA_PEAK_TFLOPS[tag]:.0f}), status {st}")
+         f"{MFMA_PEAK_TFLOPS[tag]:.0f}; labels alone {lms:.2f} ms, {entry['assign_labels_frac_mfma']:.3f}), status {st}")
     return entry, (Xq, E)
 
 

@@ -340,14 +340,18 @@ def kmpp_assign_workspace_bytes(N: int, d: int, K: int, dtype: int = KMPP_F32) -
 def kmpp_assign(X: torch.Tensor, C: torch.Tensor, *, X_exp=None, dtype: int = KMPP_F32, out_labels=None,
                 out_mind=None, ws=None, stream=None):
     """Nearest seed of every row.  X is [N, d] in `dtype` (FP32, BF16 as
-    uint16, FP8 as uint8 with X_exp).  Returns (labels int32 [N], mind FP32 [N], ws)."""
+    uint16, FP8 as uint8 with X_exp).  Returns (labels int32 [N], mind FP32
+    [N], ws); out_mind=False asks for the labels alone (mind is then None)."""
     N, d = _check_rows(X, X_exp, dtype)
     K = _centres(C, d)
     dev = X.device
     out_labels = torch.empty(N, dtype=torch.int32, device=dev) if out_labels is None else out_labels
-    out_mind = torch.empty(N, dtype=torch.float32, device=dev) if out_mind is None else out_mind
+    if out_mind is False:
+        out_mind = None
+    else:
+        out_mind = torch.empty(N, dtype=torch.float32, device=dev) if out_mind is None else out_mind
+        _expect(out_mind, "out_mind", dtype=torch.float32, numel=N)
     _expect(out_labels, "out_labels", dtype=torch.int32, numel=N)
-    _expect(out_mind, "out_mind", dtype=torch.float32, numel=N)
     _require_cuda(X, C, X_exp, out_labels, out_mind, ws)
     if ws is None:
         ws = workspace(kmpp_assign_workspace_bytes(N, d, K, dtype), dev)

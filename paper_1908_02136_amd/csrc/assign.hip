@@ -4,9 +4,11 @@
 // score(i, j) = ||c_j||^2 - 2 <x_i, c_j> has the same argmin over j as
 // ||x_i - c_j||^2.  The products run on MFMA with FP32 accumulation:
 //   FP32 rows: v_mfma_f32_16x16x4_f32;
-//   BF16 rows: v_mfma_f32_16x16x32_bf16 against the centres split into a
-//              BF16 high part and a BF16 remainder (two products), so only
-//              the rows carry storage rounding;
+//   BF16 rows: v_mfma_f32_16x16x32_bf16 in two stages: every row against
+//              the centres' BF16 high parts (one product, the high part's
+//              rounding added to the bound), then the rows that leaves
+//              undecided against high part plus BF16 remainder (two
+//              products), so only the rows carry storage rounding;
 //   FP8 rows:  each E4M3 code converted exactly to BF16, the BF16 path, and
 //              the row's power-of-two scale applied to the product.
 // A wave owns RB blocks of 16 rows, keeps their operand fragments in
@@ -19,7 +21,8 @@
 // A row's best index is final when its score gap to the second best exceeds
 // twice the products' error bound
 //   E = (c1 d + c2) u (max_j ||c_j||^2 + 2 ||x|| max_j ||c_j||) * 1.05,
-// u = 2^-24 (FP32 accumulation; BF16 adds 2^-16 for the centre split).
+// u = 2^-24 (FP32 accumulation; BF16 adds 2^-16 for the centre split, or
+// 2^-8 ||x|| max_j ||c_j|| for the high part alone).
 // Other rows are queued and re-evaluated against every centre in the direct
 // FP32 form sum_k (x_k - c_jk)^2, ties to the smallest index.
 #include "kmpp_dev.h"
@@ -246,10 +249,11 @@ __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fm
 // top-2 update alone (largest t, ties to the smaller index).
 // Waves per SIMD the compiler must allow: FP32 rows of width 97..128 fit 128
 // registers, so four waves (measured faster than three); BF16 / FP8 rows of
-// width 65..128 three (the tail's candidate rescoring would otherwise take
-// the registers of a third wave); no constraint otherwise.
+// width 33..128 two (their two accumulator sets and the next tiles'
+// operands take more registers than three waves allow, and each wave
+// overlaps its own VALU and matrix work); no constraint otherwise.
 constexpr int assign_min_waves(int fmt, int dqk) {
-  return fmt == FMT_F32 && dqk == 32 ? 4 : (fmt != FMT_F32 && dqk == 4 ? 3 : 1);
+  return fmt == FMT_F32 && dqk == 32 ? 4 : (fmt != FMT_F32 && (dqk == 2 || dqk == 4) ? 2 : 1);
 }
 
 //
@@ -267,10 +271,16 @@ void assign_mfma_kernel(AssignParams p) {
   constexpr bool BF = FMT != FMT_F32;
   constexpr bool GATHER = BF && NP == 2;  // rows from qa
   constexpr bool FIRST = BF && NP == 1;   // undecided rows go to qa
+  // BF16 / FP8 rows wider than 64 keep their best tile's values (SAVE): four
+  // more VALU operations per tile and row block, which fit under the tile's
+  // four or more MFMA steps; narrower rows' tiles have one or two steps, and
+  // there the four direct distances of the tail cost less
+  constexpr bool SAVE = BF && DQK >= 4;
   constexpr int S = DQK;                                  // MFMA steps per centre tile (per product)
   constexpr int TBG = BF ? 2 * S * 64 * 16 : S * 64 * 4;  // bytes of one packed centre tile (both parts)
   constexpr int TB = BF ? NP * S * 64 * 16 : TBG;         // bytes of the parts this stage stages in LDS
-  constexpr int TPC = TB >= 16384 ? 1 : 16384 / TB;       // tiles per chunk
+  constexpr int G = TB >= 16384 ? 2 : 4;                  // BF16 / FP8: tiles per group (see below)
+  constexpr int TPC = BF ? (TB * G >= 16384 ? G : 16384 / TB) : (TB >= 16384 ? 1 : 16384 / TB);  // tiles per chunk
   constexpr int CHB = TPC * TB;                           // bytes per chunk
   constexpr int LPT = CHB / (256 * 16);                  // 16-byte loads per thread per chunk
   static_assert(CHB % (256 * 16) == 0, "chunk is a whole number of 16-byte loads per thread");
@@ -384,15 +394,17 @@ void assign_mfma_kernel(AssignParams p) {
   }
 
   // ---- per row block (this lane's centres): the largest t so far (m1),
-  // the tile holding it (tb), and the largest t outside that tile's four
-  // values of this lane (m2)
+  // the tile holding it (tb), this lane's four values of that tile (bv),
+  // and the largest t outside those four values (m2)
   float m1[RB], m2[RB];
   int tb[RB];
+  v4f bv[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     m1[rb] = -INFINITY;
     m2[rb] = -INFINITY;
     tb[rb] = -1;
+    bv[rb] = v4f{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
   }
 
   // ---- centre chunks through LDS
@@ -419,19 +431,102 @@ void assign_mfma_kernel(AssignParams p) {
     for (int i = 0; i < LPT; ++i) sbuf[b][i * 256 + tid] = pre[i];
     if (tid < TPC * 4) scn[b][tid] = pcn;
   };
+  // tile tg's four values per row block enter as one: their maximum moves
+  // (m1, tb, bv, m2) -- the new m2 is the median of (m1, m2, tile maximum);
+  // six VALU operations per four values, ten where the values are saved
+  // (FP32 rows keep none: their matrix-core work per tile is eight times
+  // longer, and the registers would cost them a wave per SIMD).  A NaN value
+  // makes the tile maximum NaN: no compare holds, and med3 then returns the
+  // smaller of m1 and m2, so the state stays unchanged; a tile of -inf
+  // values changes nothing.
+  auto epilogue = [&](int tg, const v4f(&acc)[RB]) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      // both arms of each choice are plain values (so each compiles to a
+      // select, not a branch)
+      const v4f x = acc[rb];
+      const float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+      const float om1 = m1[rb], om2 = m2[rb];
+      const int otb = tb[rb];
+      const float tmax = max4(x0, x1, x2, x3);
+      m2[rb] = __builtin_amdgcn_fmed3f(om1, om2, tmax);
+      const bool gt = tmax > om1;
+      tb[rb] = gt ? tg : otb;
+      m1[rb] = gt ? tmax : om1;
+      if constexpr (SAVE) {
+        const v4f ob = bv[rb];
+        const float b0 = ob[0], b1 = ob[1], b2 = ob[2], b3 = ob[3];
+        const float n0 = gt ? x0 : b0, n1 = gt ? x1 : b1, n2 = gt ? x2 : b2, n3 = gt ? x3 : b3;
+        bv[rb] = v4f{n0, n1, n2, n3};
+      }
+    }
+  };
   gload(0);
   sstore(0);
   if (tid == 0) s_nf = 0;
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) gload(c + 1);
-    const int tn = min(TPC, Kt - c * TPC);
-    // products of tile t into acc (the chain starts from -||c_j||^2 / 2)
-    auto products = [&](int t, v4f(&acc)[RB]) {
-      const uint4 c4 = scn[c & 1][t * 4 + q];  // chain starts of this lane's centres j0..j0+3
-      const v4f init = v4f{__uint_as_float(c4.x), __uint_as_float(c4.y), __uint_as_float(c4.z),
-                           __uint_as_float(c4.w)};
-      if constexpr (FMT == FMT_F32) {
+  if constexpr (BF) {
+    // BF16 / FP8 rows: tiles in groups of G, the products of one tile issued
+    // before the previous tile's values are folded in, so each wave's VALU
+    // work overlaps its own matrix-core work (two accumulator sets).  The
+    // centres are padded to a multiple of 64 (chain starts -inf), so every
+    // chunk holds a whole number of groups.
+    constexpr int NF = NP * S;
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) gload(c + 1);
+      const int tn = min(TPC, Kt - c * TPC);  // a multiple of G
+      const uint4* sb = &sbuf[c & 1][0];
+      const uint4* sc = &scn[c & 1][0];
+      auto frag = [&](int t, v8bf(&cf)[NF], v4f& init) {
+        const uint4 c4 = sc[t * 4 + q];
+        init = v4f{__uint_as_float(c4.x), __uint_as_float(c4.y), __uint_as_float(c4.z), __uint_as_float(c4.w)};
+        const uint4* bp = sb + (t * NF) * 64 + lane;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) cf[f] = __builtin_bit_cast(v8bf, bp[f * 64]);
+      };
+      auto products = [&](const v8bf(&cf)[NF], const v4f& init, v4f(&acc)[RB]) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cf[f], a[rb][f % S], f == 0 ? init : acc[rb], 0, 0, 0);
+      };
+      for (int t = 0; t < tn; t += G) {
+        const int tg = c * TPC + t;
+        v8bf f0[NF], f1[NF];
+        v4f i0, i1, A[RB], B[RB];
+        frag(t, f0, i0);
+        frag(t + 1, f1, i1);
+        products(f0, i0, A);
+        if constexpr (G == 4) {
+          frag(t + 2, f0, i0);
+          products(f1, i1, B);
+          epilogue(tg, A);
+          frag(t + 3, f1, i1);
+          products(f0, i0, A);
+          epilogue(tg + 1, B);
+          products(f1, i1, B);
+          epilogue(tg + 2, A);
+          epilogue(tg + 3, B);
+        } else {
+          products(f1, i1, B);
+          epilogue(tg, A);
+          epilogue(tg + 1, B);
+        }
+      }
+      if (c + 1 < nch) sstore((c + 1) & 1);
+      __syncthreads();
+    }
+  } else {
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) gload(c + 1);
+      const int tn = min(TPC, Kt - c * TPC);
+      for (int t = 0; t < tn; ++t) {
+        // products of tile t (the chain starts from -||c_j||^2 / 2)
+        const uint4 c4 = scn[c & 1][t * 4 + q];  // chain starts of this lane's centres j0..j0+3
+        const v4f init = v4f{__uint_as_float(c4.x), __uint_as_float(c4.y), __uint_as_float(c4.z),
+                             __uint_as_float(c4.w)};
+        v4f acc[RB];
         const float* bp = reinterpret_cast<const float*>(&sbuf[c & 1][0]) + (t * S) * 64 + lane;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -440,75 +535,71 @@ void assign_mfma_kernel(AssignParams p) {
           for (int rb = 0; rb < RB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv, a[rb][s], s == 0 ? init : acc[rb], 0, 0, 0);
         }
-      } else {
-        const uint4* bp = &sbuf[c & 1][(t * NP * S) * 64 + lane];
-#pragma unroll
-        for (int hp = 0; hp < NP; ++hp)
-#pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const v8bf cv = __builtin_bit_cast(v8bf, bp[(hp * S + s) * 64]);
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-              acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cv, a[rb][s], (hp == 0 && s == 0) ? init : acc[rb],
-                                                                0, 0, 0);
-          }
+        epilogue(c * TPC + t, acc);
       }
-    };
-    // tile t's four values per row block enter as one: their maximum moves
-    // (m1, tb, m2) -- the new m2 is the median of (m1, m2, tile maximum);
-    // six VALU operations per four values (a NaN value makes the tile
-    // maximum NaN: no compare holds, and med3 then returns the smaller of
-    // m1 and m2, so m1, tb and m2 stay unchanged)
-    auto epilogue = [&](int t, const v4f(&acc)[RB]) {
-      const int tg = c * TPC + t;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const float tmax = max4(acc[rb][0], acc[rb][1], acc[rb][2], acc[rb][3]);
-        m2[rb] = __builtin_amdgcn_fmed3f(m1[rb], m2[rb], tmax);
-        const bool gt = tmax > m1[rb];
-        tb[rb] = gt ? tg : tb[rb];
-        m1[rb] = gt ? tmax : m1[rb];
-      }
-    };
-    for (int t = 0; t < tn; ++t) {
-      v4f acc[RB];
-      products(t, acc);
-      epilogue(t, acc);
+      if (c + 1 < nch) sstore((c + 1) & 1);
+      __syncthreads();
     }
-    if (c + 1 < nch) sstore((c + 1) & 1);
-    __syncthreads();
   }
 
-  // ---- merged over the four lane groups of a row (lanes col + 16 q): the
-  // group with the largest m1 (ties: the smaller centre index) gives the
-  // candidates, its four centres of tile tb; every other value of the row
-  // is at most `out` (its m2, the other groups' m1)
-  float b1[RB], out[RB];
+  // ---- per lane, the largest of its four saved values (ties: the smaller
+  // index; it equals m1) and the largest of the other three; then merged
+  // over the four lane groups of a row (lanes col + 16 q): the group with
+  // the largest m1 (ties: the smaller centre index) gives the candidate bj.
+  // Every other value of the row is at most oa (the owner's other saved
+  // values and m2, the other groups' m1); every value outside the owner's
+  // four saved centres is at most ot.  All four lanes of a row end with the
+  // same b1, bj, oa, ot.
+  float b1[RB], oa[RB], ot[RB];
   int bj[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
+    float v1 = bv[rb][0], v2 = -INFINITY;
+    int ix = 0;
+#pragma unroll
+    for (int e = 1; e < 4; ++e) {
+      const float v = bv[rb][e];
+      if (v > v1) {
+        v2 = v1;
+        v1 = v;
+        ix = e;
+      } else {
+        v2 = fmaxf(v2, v);
+      }
+    }
     b1[rb] = m1[rb];
-    out[rb] = m2[rb];
-    bj[rb] = tb[rb] >= 0 ? tb[rb] * 16 + 4 * q : INT_MAX;
+    // (without saved values no row is decided without the direct
+    // distances of its four candidates)
+    oa[rb] = SAVE ? fmaxf(m2[rb], v2) : INFINITY;
+    ot[rb] = m2[rb];
+    bj[rb] = tb[rb] >= 0 ? tb[rb] * 16 + 4 * q + ix : INT_MAX;
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
       const float o1 = __shfl_xor(b1[rb], o, 64);
       const int oj = __shfl_xor(bj[rb], o, 64);
-      const float oo = __shfl_xor(out[rb], o, 64);
+      const float ooa = __shfl_xor(oa[rb], o, 64);
+      const float oot = __shfl_xor(ot[rb], o, 64);
       if (o1 > b1[rb] || (o1 == b1[rb] && oj < bj[rb])) {
-        out[rb] = fmaxf(b1[rb], oo);
+        oa[rb] = fmaxf(b1[rb], ooa);
+        ot[rb] = fmaxf(b1[rb], oot);
         b1[rb] = o1;
         bj[rb] = oj;
       } else {
-        out[rb] = fmaxf(out[rb], o1);
+        oa[rb] = fmaxf(oa[rb], o1);
+        ot[rb] = fmaxf(ot[rb], o1);
       }
     }
   }
 
-  // ---- per row: ||x||, the bound, and the direct FP32 distances to the
-  // four candidates over this lane's quarter of the row (the row values are
-  // the fragments already in registers, exact), summed over the four lane
-  // groups; the nearest candidate (ties: the smaller index) is the label
+  // ---- per row: ||x|| and the bound.  A row whose best score is ahead of
+  // every other by more than the bound is decided (label bj); one ahead of
+  // every score outside the owner's four saved centres is decided among
+  // those four by their direct FP32 distances (ties: the smaller index);
+  // other rows are queued.  The direct distance of the label is computed
+  // when it is returned.  Direct distances run over this lane's quarter of
+  // the row (the row values are the fragments in registers, exact) and are
+  // summed over the four lane groups, so the branches around them are taken
+  // by whole waves.
   const float cmax2 = *p.cmax2;
   const float cmax = sqrtf(cmax2);
   constexpr float kGrowth = 1.05f;
@@ -519,8 +610,6 @@ void assign_mfma_kernel(AssignParams p) {
     x2 += __shfl_xor(x2, 16, 64);
     x2 += __shfl_xor(x2, 32, 64);
     const int64_t row = rowv[rb];
-    // t values: the score gap is twice the t gap
-    const float gap = 2.0f * (b1[rb] - out[rb]);
     const float xn = sqrtf(x2) * 1.0001f;
     const float mag = cmax2 + 2.0f * xn * cmax;
     // score error bound: FP32 accumulation over the products and the chain
@@ -530,16 +619,16 @@ void assign_mfma_kernel(AssignParams p) {
                                                    : (float)(2 * p.dp + 8) * 0x1p-24f + 0x1p-16f;
     float E = unit * mag * kGrowth;
     if constexpr (FIRST) E += 0x1p-8f * xn * cmax * kGrowth;
-    const bool sure = gap > 2.0f * E && bj[rb] < p.K;
-    // one candidate at a time (few registers: the tail must not lower the
-    // main loop's occupancy); a lane's quarter of a candidate row is
-    // contiguous, read with 16-byte loads where it lies wholly inside the
-    // row, else element by element (index clamped, positions past d masked)
-    float dbest = INFINITY;
-    int best = INT_MAX;
-    for (int v = 0; v < 4; ++v) {
-      const int j = bj[rb] < p.K ? bj[rb] + v : 0;
-      const float* crow = p.C + (int64_t)min(j, p.K - 1) * p.d;
+    // t values: score gaps are twice the t gaps
+    const bool sure_a = 2.0f * (b1[rb] - oa[rb]) > 2.0f * E && bj[rb] < p.K;
+    const bool sure_t = 2.0f * (b1[rb] - ot[rb]) > 2.0f * E && bj[rb] < p.K;
+    const bool four = sure_t && !sure_a;
+    // direct distance of this row to centre j (clamped into range); a lane's
+    // quarter of a centre row is contiguous, read with 16-byte loads where
+    // it lies wholly inside the row, else element by element (positions
+    // past d masked)
+    auto qdist = [&](int j) {
+      const float* crow = p.C + (int64_t)min(max(j, 0), p.K - 1) * p.d;
       float dd = 0.0f;
       if (QV % 4 == 0 && (p.d & 3) == 0 && (q + 1) * QV <= p.d) {
         const float4* c4 = reinterpret_cast<const float4*>(crow + q * QV);
@@ -563,19 +652,37 @@ void assign_mfma_kernel(AssignParams p) {
       }
       dd += __shfl_xor(dd, 16, 64);
       dd += __shfl_xor(dd, 32, 64);
-      if (j < p.K && bj[rb] < p.K && dd < dbest) {
-        dbest = dd;
-        best = j;
+      return dd;
+    };
+    int best = bj[rb];
+    float dbest = 0.0f;
+    if (__ballot(four) != 0ull) {
+      const int j0 = four ? (bj[rb] & ~3) : 0;  // the owner's four saved centres
+      float db = INFINITY;
+      int bb = INT_MAX;
+      for (int v = 0; v < 4; ++v) {
+        const float dd = qdist(j0 + v);
+        if (j0 + v < p.K && dd < db) {
+          db = dd;
+          bb = j0 + v;
+        }
+      }
+      if (four) {
+        best = bb;
+        dbest = db;
       }
     }
-    const float dd = dbest;
+    if (p.mind != nullptr && __ballot(sure_a) != 0ull) {
+      const float dd = qdist(sure_a ? bj[rb] : 0);
+      if (sure_a) dbest = dd;
+    }
     const bool mine = q == 0 && row >= 0;
-    if (mine && sure) {
+    if (mine && sure_t) {
       p.labels[row] = best;
-      if (p.mind) p.mind[row] = dd;
+      if (p.mind) p.mind[row] = dbest;
     }
     // rows for the recheck are collected in LDS
-    const bool flag = mine && !sure;
+    const bool flag = mine && !sure_t;
     const unsigned long long fm = __ballot(flag);
     if (fm) {
       int base = 0;
@@ -909,7 +1016,8 @@ int assign_steps(int d, int dtype) {
 
 AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   AssignLayout L;
-  L.Kp = round_up(K, 16);
+  // BF16 / FP8: a multiple of 64, so the main loop's groups of tiles are whole
+  L.Kp = round_up(K, dtype == KMPP_F32 ? 16 : 64);
   const int steps = assign_steps(d, dtype);
   L.dp = steps ? 4 * (dtype == KMPP_F32 ? 1 : 8) * steps : round_up(d, 4);
   size_t off = sizeof(Ctl);
@@ -961,7 +1069,7 @@ hipError_t dispatch_main(AssignParams& p, int steps, hipStream_t stream) {
   if constexpr (FMT == FMT_F32) {
     switch (steps) {
       case 1: return launch_main<FMT, 1, 4>(p, stream);
-      case 2: return launch_main<FMT, 2, 4>(p, stream);
+      case 2: return launch_main<FMT, 2, 8>(p, stream);
       case 4: return launch_main<FMT, 4, 4>(p, stream);
       case 8: return launch_main<FMT, 8, 4>(p, stream);
       case 16: return launch_main<FMT, 16, 4>(p, stream);

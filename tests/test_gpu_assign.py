@@ -173,3 +173,41 @@ def test_large_norm_centres_near_rows(kl, dtype):
         lab, mind = run_assign(kl, q, Ch.cuda(), dtype=kl.KMPP_BF16)
         Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
     check_assign(Xd, Ch.numpy(), lab, mind)
+
+
+@pytest.mark.parametrize("N", [30_011, 70_001])
+def test_recheck_queue_short_and_long(kl, N):
+    # every row near one far point: the matrix-core bound decides none of
+    # them, so all go to the direct-form recheck (queues of 30,011 and
+    # 70,001 rows, more than one pass of the recheck grid)
+    d, K = 64, 300
+    g = torch.Generator().manual_seed(N)
+    Ch = (500.0 + torch.randn((K, d), generator=g)).float()
+    Xh = (500.0 + torch.randn((N, d), generator=g)).float()
+    print("assign recheck queue", N, flush=True)
+    lab, mind = run_assign(kl, Xh.cuda(), Ch.cuda())
+    check_assign(Xh.numpy(), Ch.numpy(), lab, mind)
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+@pytest.mark.parametrize("d", [16, 64, 128])
+def test_labels_without_distances(kl, dtype, d):
+    # no distance output (a NULL out_mind): the same labels as with it, and
+    # the oracle's on the stored rows
+    N, K = 20_011, 300
+    Xh = kmpp_synth.gaussian(N, d, seed=d + 7, scale=3.0)
+    Ch = Xh[torch.randperm(N, generator=torch.Generator().manual_seed(d))[:K]].contiguous()
+    X, E = (Xh.cuda(), None) if dtype == 0 else kl.kmpp_quantize(Xh.cuda(), dtype)
+    print("assign labels only", dtype, d, flush=True)
+    lab1, mind1, _ = kl.kmpp_assign(X, Ch.cuda(), X_exp=E, dtype=dtype)
+    lab0, mind0, _ = kl.kmpp_assign(X, Ch.cuda(), X_exp=E, dtype=dtype, out_mind=False)
+    torch.cuda.synchronize()
+    assert mind0 is None
+    assert torch.equal(lab0, lab1)
+    if dtype == 0:
+        Xd = Xh.numpy()
+    elif dtype == 1:
+        Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
+    else:
+        Xd = oracle.fp8_dequantize_rows(*oracle.fp8_quantize_rows(Xh.numpy()))
+    check_assign(Xd, Ch.numpy(), lab0.cpu().numpy(), mind1.cpu().numpy())
