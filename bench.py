@@ -590,6 +590,21 @@ ASSIGN_CASES = {
 }
 
 
+def seed_only(kl, name, K):
+    """Counter-collection driver: the calibration copy bench.py's main run
+    makes (256 MiB read, 256 MiB written), then one seeding of the first K
+    seeds of the plain (1M x 32) or large (16.7M x 64) FP32 workload."""
+    import kmpp_synth
+    cal = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    torch.empty_like(cal).copy_(cal)
+    del cal
+    w = kmpp_synth.plain(device="cuda") if name == "plain" else kmpp_synth.large(device="cuda")
+    torch.cuda.synchronize()
+    kl.kmpp_seed(w.X, min(K, w.K), 0)
+    torch.cuda.synchronize()
+    print("seed-only done", name, w.N, w.d, min(K, w.K), flush=True)
+
+
 def assign_only(kl, case):
     """Counter-collection driver: N(0, 1) rows, the first K rows as centres,
     one untimed and three more assignments."""
@@ -618,6 +633,10 @@ def main():
     ap.add_argument("--step-only", action="store_true", help="the headline step alone (profiler runs)")
     ap.add_argument("--assign-only", default=None, choices=sorted(ASSIGN_CASES),
                     help="four assignments of one case, then exit (counter runs)")
+    ap.add_argument("--seed-only", default=None, choices=["plain", "large"],
+                    help="a plain copy of 256 MiB, then one seeding of the first --seed-k seeds of a workload "
+                         "(counter runs)")
+    ap.add_argument("--seed-k", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
@@ -633,6 +652,9 @@ def main():
     torch.cuda.set_device(0)
     if args.assign_only:
         assign_only(kl, args.assign_only)
+        return
+    if args.seed_only:
+        seed_only(kl, args.seed_only, args.seed_k)
         return
 
     # a plain device copy of known size (256 MiB read, 256 MiB written):
