@@ -97,10 +97,11 @@ __device__ __forceinline__ uint64_t wait_for(uint64_t* addr, uint64_t mask, uint
         return want;
       }
     }
-    if (i < 64)
-      __builtin_amdgcn_s_sleep(1);
-    else
-      __builtin_amdgcn_s_sleep(40);
+    // the shortest sleep between polls: a gang's members wait for each
+    // other every seed step, and longer sleeps (40 x 64 clocks after the
+    // first 64 polls) measured 51.7 against 49.3 ms for the 512-instance
+    // batch
+    __builtin_amdgcn_s_sleep(1);
     v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return v;

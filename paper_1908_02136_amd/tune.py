@@ -119,7 +119,7 @@ def tune_batched(kl, quick):
     Xs = [kmpp_synth.batched_instance(b, spec.N[b], spec.d[b], spec.K[b], device="cuda") for b in range(512)]
     best = None
     path = os.path.join(HERE, "_tune_tmp.txt")
-    grid = [(w, a, sw) for w in (1, 2, 3, 4) for a in (0.25, 0.5, 1.0, 2.0) for sw in (3.0, 6.0, 12.0)]
+    grid = [(w, a, sw) for w in (2, 3, 4) for a in (0.0625, 0.125, 0.25, 0.5, 1.0) for sw in (0.75, 1.5, 3.0, 6.0)]
     if quick:
         grid = [(w, 1.0, 6.0) for w in (1, 2, 3, 4)]
     for wpc, alpha, syncw in grid:
