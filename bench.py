@@ -121,7 +121,11 @@ class PassEvents:
 
 
 def seed_pass_rate(kl, X, K, row_bytes, reps=2, **kw):
-    """Average seed-pass duration (ms) and algorithmic GB/s from per-pass events."""
+    """Average seed-pass duration (ms) and algorithmic GB/s from per-pass
+    events.  The draws run in their own kernel here, so the events time the
+    pass's streaming alone (a pass that draws at its start would include the
+    draw)."""
+    kw.setdefault("draw", kl.KMPP_DRAW_KERNEL)
     ev = PassEvents(K)
     durs = []
     for _ in range(reps):
@@ -266,7 +270,9 @@ def memory_spaces(kl, reps=3):
         grid = {}
         for rn, rl in kl.ROW_PATHS.items():
             for cn, cs in kl.CENTRE_SOURCES.items():
-                kw = dict(threads=256, loads_per_lane=8, row_loads=rl, centre_source=cs)
+                # one draw placement for every combination (the draw kernel: the
+                # passes of the comparison stream and nothing else)
+                kw = dict(threads=256, loads_per_lane=8, row_loads=rl, centre_source=cs, draw=kl.KMPP_DRAW_KERNEL)
                 kl.kmpp_seed(X, K, 0, **kw)
                 torch.cuda.synchronize()
                 ms = time_events(lambda: kl.kmpp_seed(X, K, 0, **kw), reps)

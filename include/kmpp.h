@@ -98,10 +98,11 @@ enum { KMPP_ROWS_CACHED = 0, KMPP_ROWS_NONTEMPORAL = 1, KMPP_ROWS_BUFFER = 2 };
 enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
 
 /*
- * Where each draw runs (kmpp_seed_opts.draw).  Both follow the same steps
+ * Where each draw runs (kmpp_seed_opts.draw).  All follow the same steps
  * in the same order, so for one launch shape they pick the same seeds.
  *   KMPP_DRAW_AUTO    PASS where a pass has at most 256 tiles, else the
- *                     tuning table's choice for (format, d), else KERNEL
+ *                     tuning table's choice for (format, d), else LEAD up to
+ *                     4096 tiles, else KERNEL
  *   KMPP_DRAW_PASS    every workgroup of pass m+1 draws seed m at its start
  *                     from pass m's D and tile sums (one launch per seed;
  *                     passes then write D and tile sums to alternating
@@ -111,8 +112,14 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *                     share that keeps the pass's occupancy), else KERNEL.
  *   KMPP_DRAW_KERNEL  a one-workgroup draw kernel after each pass (two
  *                     launches per seed; D updated in place where it changed)
+ *   KMPP_DRAW_LEAD    workgroup 0 of pass m+1 draws seed m at its start and
+ *                     publishes the index; the pass's other workgroups wait
+ *                     for it (bounded: KMPP_E_TIMEOUT after one second) with
+ *                     their first rows in flight (one launch per seed; D and
+ *                     tile sums in place).  Exact widths, unweighted seeding;
+ *                     else KERNEL.
  */
-enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2 };
+enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2, KMPP_DRAW_LEAD = 3 };
 
 /* Optional knobs of kmpp_seed (pass NULL for defaults). */
 typedef struct kmpp_seed_opts {
@@ -132,7 +139,8 @@ typedef struct kmpp_seed_opts {
                            (profiling only) */
   int32_t centre_source;/* where the passes take the current centre from: 0 (default: LDS),
                            KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR or KMPP_CENTRE_GLOBAL */
-  int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS or KMPP_DRAW_KERNEL */
+  int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS, KMPP_DRAW_KERNEL or
+                           KMPP_DRAW_LEAD */
   double* out_sumD;     /* device FP64 [K] or NULL: [m] (m >= 1) = the sum of D that draw m
                            inverted (the denominator of P(n_l) in Algorithm 1, summed in
                            FP64 in the fixed tile order); [0] = 0 */
@@ -344,8 +352,8 @@ int kmpp_graph_destroy(kmpp_graph g);
 
 /* Tuning table: text lines
  * "seed <dtype> <d> <threads> <rows_per_tile> [<loads_per_lane> <row path> [<draw>]]"
- * override the built-in choices for the seed pass (draw: KMPP_DRAW_PASS or
- * KMPP_DRAW_KERNEL); lines
+ * override the built-in choices for the seed pass (draw: KMPP_DRAW_PASS,
+ * KMPP_DRAW_KERNEL or KMPP_DRAW_LEAD); lines
  * "batched <key> <value>" (keys wg_per_cu, chip_gbs, sync1_us, syncw_us,
  * alpha) set the batched planner's cost model; "batched wait_ms <v>" sets
  * the budget of one gang wait (v < 0: automatic, eight times the plan's

@@ -28,7 +28,7 @@ KMPP_ROWS_CACHED, KMPP_ROWS_NONTEMPORAL, KMPP_ROWS_BUFFER = 0, 1, 2
 KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR, KMPP_CENTRE_GLOBAL = 1, 2, 3
 ROW_PATHS = {"cached": KMPP_ROWS_CACHED, "nontemporal": KMPP_ROWS_NONTEMPORAL, "buffer": KMPP_ROWS_BUFFER}
 CENTRE_SOURCES = {"lds": KMPP_CENTRE_LDS, "scalar": KMPP_CENTRE_SCALAR, "global": KMPP_CENTRE_GLOBAL}
-KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL = 0, 1, 2
+KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL, KMPP_DRAW_LEAD = 0, 1, 2, 3
 OK, W_DEGENERATE = 0, 1
 E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT, E_TOO_LARGE = -1, -2, -3, -4, -5, -6, -7
 MAX_D = 4096
@@ -249,8 +249,9 @@ def kmpp_seed(X: torch.Tensor, K: int, seed: int = 0, *, out_centers=None, out_D
     (idx int64 [K], centers FP32 [K, d], D FP32 [N], workspace).
     ``row_loads`` (KMPP_ROWS_*) and ``centre_source`` (KMPP_CENTRE_*) pick
     the memory spaces of the passes (-1 / 0: tuned default); ``draw``
-    (KMPP_DRAW_*) runs each draw at the start of the next pass or in a
-    kernel of its own; ``out_recheck`` (FP32 [2K]) and ``out_sumD`` (FP64
+    (KMPP_DRAW_*) runs each draw at the start of the next pass (by every
+    workgroup, or by its first for all) or in a kernel of its own;
+    ``out_recheck`` (FP32 [2K]) and ``out_sumD`` (FP64
     [K]) receive the per-draw diagnostics described in kmpp.h."""
     N, d = _rows(X)
     _expect(X, "X", dtype=torch.float32)

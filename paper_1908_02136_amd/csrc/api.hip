@@ -42,6 +42,7 @@ constexpr int kDrawAtStartTiles = 2048;
 // Up to this many tiles the automatic choice is the draw at pass start (it
 // was faster on every measured shape; with ~1000 tiles the draw kernel was).
 constexpr int kFewTiles = 256;
+constexpr int kLeadTiles = 4096;
 
 // Rows larger than the 256 MiB last-level cache are streamed with
 // non-temporal loads; smaller ones stay cached between passes.
@@ -104,10 +105,16 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   *ntiles_out = (int)((N + r - 1) / r);
   // the caller's choice; else the draw at pass start wherever a pass has few
   // tiles (it saves a launch per seed and reads little), else the tuned
-  // choice (taken at one size per format and width), else the draw kernel
+  // choice (taken at one size per format and width), else the lead
+  // workgroup's draw up to kLeadTiles tiles (faster than the draw kernel
+  // there: -7 % per seed on 977 tiles, -1 to -3 % on 2048-4096) and the draw
+  // kernel beyond (0.2-2 % faster on 8192 tiles, where the one drawing
+  // workgroup reads 64 KiB of tile sums alone)
   int draw = opts && opts->draw ? opts->draw : KMPP_DRAW_AUTO;
   if (draw == KMPP_DRAW_AUTO)
-    draw = *ntiles_out <= kFewTiles ? KMPP_DRAW_PASS : (tuned_draw ? tuned_draw : KMPP_DRAW_KERNEL);
+    draw = *ntiles_out <= kFewTiles
+               ? KMPP_DRAW_PASS
+               : (tuned_draw ? tuned_draw : (*ntiles_out <= kLeadTiles ? KMPP_DRAW_LEAD : KMPP_DRAW_KERNEL));
   *draw_out = draw;
   return KMPP_OK;
 }
@@ -157,7 +164,8 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   const size_t draw_lds = std::max(sizeof(double) * (size_t)ntiles, sizeof(float) * (size_t)rpt);
   const bool at_start = draw == KMPP_DRAW_PASS && v->fn_drawer && !wts && ntiles <= kDrawAtStartTiles &&
                         draw_lds <= (size_t)160 * 1024 * v->nt / 2048;
-  const void* pass_fn = at_start ? v->fn_drawer : v->fn;
+  const bool lead = draw == KMPP_DRAW_LEAD && v->fn_lead && !wts;
+  const void* pass_fn = at_start ? v->fn_drawer : (lead ? v->fn_lead : v->fn);
   // its buffers: pass m writes D to Dbuf[(K - m) % 2], so pass K ends in the
   // caller's D, and its tile sums to Tbuf[m % 2]
   float* const Dbuf[2] = {p.D, reinterpret_cast<float*>(ws + L.D2)};
@@ -189,7 +197,7 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
                                 ev[2 * (m - 1) + 1], 0)
            : hipLaunchKernel(pass_fn, grid, dim3((unsigned)v->nt), args, shmem, stream);
     if (le != hipSuccess) return KMPP_E_HIP;
-    if (m < K && !at_start &&
+    if (m < K && !at_start && !lead &&
         hipLaunchKernel(seed_draw_fn(wts != nullptr), dim3(1), dim3((unsigned)seed_draw_threads()), args, 0, stream) !=
             hipSuccess)
       return KMPP_E_HIP;
@@ -219,7 +227,7 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
     if (!Xq || !aligned(Xq, 16)) return KMPP_E_INVALID;
     if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
   }
-  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_KERNEL)) return KMPP_E_INVALID;
+  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_LEAD)) return KMPP_E_INVALID;
   return seed_run(X, N, d, K, seed, opts ? opts->instance : 0u, 0u, nullptr, out_centers, out_D, out_idx, Xq, Xq_exp,
                   dtype, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream_));
 }
@@ -379,7 +387,7 @@ int kmpp_tune_load(const char* path) {
     double val;
     const int got = sscanf(line, "%31s %d %d %d %d %d %d %d", kind, &dt, &d, &nt, &rpt, &u, &ntl, &draw);
     if (got >= 5 && strcmp(kind, "seed") == 0 && valid_dtype(dt) && (nt == 256 || nt == 512) && rpt > 0 &&
-        (u == 0 || u == 8 || u == 16) && ntl >= -1 && ntl <= 1 && draw >= 0 && draw <= KMPP_DRAW_KERNEL) {
+        (u == 0 || u == 8 || u == 16) && ntl >= -1 && ntl <= 1 && draw >= 0 && draw <= KMPP_DRAW_LEAD) {
       g_tune[{dt, d}] = SeedTune{nt, rpt, u, ntl, draw};
       ++n;
     } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "batched") == 0 &&

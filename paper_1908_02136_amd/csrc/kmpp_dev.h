@@ -27,7 +27,8 @@ struct Ctl {
   uint32_t arrive;     // reserved (0)
   uint32_t nflag;      // assignment: rows queued for the direct-form recheck
   uint32_t nqueue;     // assignment, BF16/FP8 rows: rows the first stage left to the second
-  uint32_t pad[60];
+  uint64_t lead;       // seed loop, lead-workgroup draw: (pass << 32) | drawn row
+  uint32_t pad[58];
 };
 static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 

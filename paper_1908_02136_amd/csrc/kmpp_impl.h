@@ -52,6 +52,7 @@ struct SeedVariant {
   int rows_per_iter; // rows one workgroup covers per loop iteration
   const void* fn;
   const void* fn_drawer;  // the same pass drawing the previous seed at its start, or null
+  const void* fn_lead;    // the same pass with workgroup 0 drawing the previous seed for all, or null
 };
 
 const std::vector<SeedVariant>& seed_variants();

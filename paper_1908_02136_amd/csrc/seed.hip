@@ -7,9 +7,11 @@
 // cumulative distribution of D (tile sums, then the owning tile's rows) at
 // t = u_m * sum(D), either by every workgroup of pass m+1 at its start (one
 // launch per seed; pass m+1 then writes D and its tile sums to the other of
-// two buffers, so pass m's stay intact while any workgroup still draws) or
-// by a one-workgroup draw kernel between the passes (two launches per seed;
-// weighted seeding, very many tiles, or where the tuning table says so).
+// two buffers, so pass m's stay intact while any workgroup still draws), by
+// workgroup 0 of pass m+1 alone, which publishes the index to the others
+// (one launch per seed, D in place: nobody writes D or a tile sum before the
+// index is out), or by a one-workgroup draw kernel between the passes (two
+// launches per seed; weighted seeding, or where the tuning table says so).
 // Pass m+1 reads that original FP32 row, broadcasts it from LDS and stores
 // it in out_centers[m].  Nothing returns to the host between seeds.
 //
@@ -29,6 +31,9 @@
 
 namespace kmpp {
 
+// wait budget of the lead-workgroup draw: 1 s of the 100 MHz real-time counter
+constexpr uint64_t kLeadWaitTicks = 100000000ull;
+
 // ---------------------------------------------------------------- S1
 // First seed: i0 = min(floor(u_0 N), N-1); resets the status word.
 __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
@@ -36,6 +41,7 @@ __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
   if (threadIdx.x == 0) {
     p.ctl->status = KMPP_OK;
     p.ctl->arrive = 0u;
+    p.ctl->lead = 0ull;
     if (p.sumD) p.sumD[0] = 0.0;
     const double u0 = draw_uniform(p.seed, 0u, p.inst);
     const int64_t i0 = uniform_index(u0, p.N);
@@ -289,22 +295,26 @@ __device__ __forceinline__ void stage_to_lds(const T* __restrict__ src, L* dst, 
   }
 }
 
-template <int NT>
+template <int NT, bool STAGE = true>
 __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
   constexpr int NW = NT / 64;
   __shared__ double sh[NW];
   __shared__ int2 shm[NW];
   __shared__ float shf[NW];
   __shared__ double s_lo;
-  double* ts = reinterpret_cast<double*>(lds);
+  const double* ts = reinterpret_cast<const double*>(lds);
   const int tid = threadIdx.x;
   const int G = p.ntiles;
   const int NONE = INT_MAX;
   const int step = p.pass - 1;
   const bool lead = blockIdx.x == 0;
 
-  stage_to_lds<NT>(p.tsum, ts, G);
-  __syncthreads();
+  if constexpr (STAGE) {
+    stage_to_lds<NT>(p.tsum, reinterpret_cast<double*>(lds), G);
+    __syncthreads();
+  } else {
+    ts = p.tsum;  // read in place (nothing writes them before the draw ends)
+  }
   // the tiles: contiguous blocks per thread, fixed-order FP64 scan
   const int per = (G + NT - 1) / NT;
   const int b0 = min(G, tid * per);
@@ -349,8 +359,9 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
     const int64_t r0 = (int64_t)tile * p.rows_per_tile;
     const int64_t r1 = min(p.N, r0 + (int64_t)p.rows_per_tile);
     const int n = (int)(r1 - r0);
-    stage_to_lds<NT>(p.D + r0, lds, n);
-    __syncthreads();
+    const float* dv = STAGE ? lds : p.D + r0;
+    if constexpr (STAGE) stage_to_lds<NT>(p.D + r0, lds, n);
+    __syncthreads();  // s_lo (and the staged D) are visible to every thread
     const double tlo = inside ? s_lo : 0.0;
     const int per2 = (n + NT - 1) / NT;
     const int j0 = min(n, tid * per2);
@@ -358,7 +369,7 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
     int found = NONE, lastrow = -1;
     double part2 = 0.0;
     for (int k = 0; k < nq; ++k) {
-      const float dk = lds[j0 + k];
+      const float dk = dv[j0 + k];
       part2 += (double)dk;
       if (dk > 0.0f) lastrow = j0 + k;
     }
@@ -366,7 +377,7 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
     if (inside) {
       double r = tlo + sc2.x;
       for (int k = 0; k < nq && found == NONE; ++k) {
-        r += (double)lds[j0 + k];
+        r += (double)dv[j0 + k];
         if (r > t) found = j0 + k;
       }
     }
@@ -406,8 +417,10 @@ __device__ int64_t draw_at_start(const SeedParams& p, float* lds) {
 // DRAWER: every workgroup first draws seed m-1 (m >= 2) from pass m-1's D
 // and tile sums; this pass writes every row's D to Dw and its tile sums to
 // tsum_w (the other buffers).  Else D is updated in place where it changed.
-template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS, bool DRAWER>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL, int NT, int RL, int CS, int DRAW>
 __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
+  constexpr bool DRAWER = DRAW == 1;
+  constexpr bool LEAD = DRAW == 2;
   using S = Streamer<FMT, CB, G, CPL, U, FULL, NT, RL>;
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) float cs[];  // centre row, d floats (CEN_LDS); the draw's staging (DRAWER)
@@ -430,6 +443,7 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   // d = 128), with DRAWER the draw's registers come on top, and the 256-thread
   // variants (those of the memory-space comparison) keep one code shape.
   constexpr bool kEarly = !DRAWER && FMT == FMT_F32 && G <= 8 && NT == 512;
+  __shared__ int64_t s_cidx;
   const int64_t base0 = t0 + (int64_t)st.wave * S::R;
   typename S::Batch b0;
   const bool early = kEarly && base0 < t1;
@@ -437,10 +451,44 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
   // centre c_{pass-1}: the original FP32 row of the previous seed (drawn
   // here first with DRAWER)
   int64_t cidx;
-  if constexpr (DRAWER)
+  if constexpr (DRAWER) {
     cidx = p.pass >= 2 ? draw_at_start<NT>(p, cs) : p.idx[0];
-  else
+  } else if constexpr (LEAD) {
+    // workgroup 0 draws seed pass-1 from the previous pass's tile sums and
+    // D, in place (no workgroup of this pass writes either before it has
+    // the index), and publishes the index tagged with the pass; the others
+    // wait for it (their first rows already in flight).  Workgroup 0 is
+    // dispatched first and waits for nobody, so every wait ends; a wait
+    // past its budget raises KMPP_E_TIMEOUT.
+    if (p.pass < 2) {
+      cidx = p.idx[0];
+    } else if (blockIdx.x == 0) {
+      cidx = draw_at_start<NT, false>(p, cs);
+      if (tid == 0)
+        __hip_atomic_store(&p.ctl->lead, ((uint64_t)(uint32_t)p.pass << 32) | (uint64_t)cidx, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (tid == 0) {
+        const uint64_t want = (uint64_t)(uint32_t)p.pass;
+        uint64_t v = __hip_atomic_load(&p.ctl->lead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while ((v >> 32) != want) {
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kLeadWaitTicks) {
+            raise_status(p.ctl, KMPP_E_TIMEOUT);
+            v = want << 32;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          v = __hip_atomic_load(&p.ctl->lead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_cidx = (int64_t)(v & 0xFFFFFFFFull);
+      }
+      __syncthreads();
+      cidx = s_cidx;
+    }
+  } else {
     cidx = p.idx[p.pass - 1];
+  }
   // every draw has raised its status by now (the last one in this
   // workgroup's own thread 0 with DRAWER, else in an earlier launch)
   if (p.status_out && p.pass == p.K && blockIdx.x == 0 && tid == 0)
@@ -507,11 +555,14 @@ static SeedVariant make_variant(int dexact) {
   v.rl = RL;
   v.cs = CS;
   v.rows_per_iter = (NT / 64) * U * (64 / G);
-  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, false>);
-  if constexpr (WITH_DRAWER)
-    v.fn_drawer = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, true>);
-  else
+  v.fn = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, 0>);
+  if constexpr (WITH_DRAWER) {
+    v.fn_drawer = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, 1>);
+    v.fn_lead = reinterpret_cast<const void*>(&seed_pass_kernel<FMT, CB, G, CPL, U, FULL, NT, RL, CS, 2>);
+  } else {
     v.fn_drawer = nullptr;
+    v.fn_lead = nullptr;
+  }
   return v;
 }
 

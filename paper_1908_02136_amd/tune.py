@@ -2,15 +2,17 @@
 
 * Seed pass: for each (storage format, d) it times whole seeding runs over a
   grid of (threads per workgroup, rows per tile, row loads in flight per
-  lane, cached or non-temporal row loads, draw at the start of the next pass
-  or in a draw kernel) and keeps the fastest;
+  lane, cached or non-temporal row loads, draw at the start of the next pass,
+  in a draw kernel or by the next pass's first workgroup for all) and keeps
+  the fastest;
 * batched planner: it times the 512-instance batch over a grid of the
   cost-model knobs (workgroups per CU, the cap on one instance's time) and
   keeps the fastest.
 
 The result is written as text lines
 ``seed <dtype> <d> <threads> <rows> <loads per lane> <non-temporal> <draw>``
-(draw: 1 at the start of the next pass, 2 draw kernel) and ``batched <key> <value>`` to
+(draw: 1 at the start of the next pass, 2 draw kernel, 3 workgroup 0 of the
+next pass for all) and ``batched <key> <value>`` to
 ``tune_table.txt`` next to the library, which the binding loads at import
 (``kmpp_tune_load``).
 
@@ -49,9 +51,9 @@ DRAW_AT_START_TILES = 2048
 
 
 def tune_draw(kl, X, K, Xq, E, dtype, nt, rpt, u, ntl):
-    """Faster draw placement (KMPP_DRAW_PASS or KMPP_DRAW_KERNEL) for one schedule."""
+    """Fastest draw placement (KMPP_DRAW_PASS, KMPP_DRAW_KERNEL or KMPP_DRAW_LEAD) for one schedule."""
     ms = {}
-    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL):
+    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL, kl.KMPP_DRAW_LEAD):
         ms[draw] = _time(lambda: kl.kmpp_seed(X, K, 0, Xq=Xq, Xq_exp=E, dtype=dtype, threads=nt, rows_per_tile=rpt,
                                               loads_per_lane=u, row_loads=ntl, draw=draw), reps=3)
         print(f"seed dtype={dtype} d={X.shape[1]} N={X.shape[0]} K={K} threads={nt} rows={rpt} u={u} nt={ntl} "
@@ -86,7 +88,7 @@ def tune_seed(kl, cases, quick, keep=None):
         best = None
         for nt in (256, 512):
             for rpt in rpt_grid:
-                draws = [kl.KMPP_DRAW_KERNEL]
+                draws = [kl.KMPP_DRAW_KERNEL, kl.KMPP_DRAW_LEAD]
                 if -(-N // rpt) <= DRAW_AT_START_TILES:
                     draws.append(kl.KMPP_DRAW_PASS)
                 for u in (8, 16):

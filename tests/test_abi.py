@@ -71,7 +71,7 @@ def test_seed_argument_checks_need_no_gpu(kl):
     # null outputs
     assert L.kmpp_seed(fake, 10, 2, 1, 0, None, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
     # unknown draw mode
-    opts = kl.SeedOpts(0, 0, 0, 0, -1, None, None, 0, 3)
+    opts = kl.SeedOpts(0, 0, 0, 0, -1, None, None, 0, 4)
     assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 0, ctypes.byref(opts), ws, 1 << 30,
                        None) == -1
 
@@ -96,10 +96,10 @@ def test_other_argument_checks_need_no_gpu(kl):
 def test_tune_file_parses(kl, tmp_path):
     p = tmp_path / "t.txt"
     p.write_text("seed 0 32 256 512\nseed 0 64 512 256\n# comment\nseed 9 1 256 1\nbogus\n"
-                 # the draw column: 1 (at pass start), 2 (kernel); 3 and -1 are rejected
-                 "seed 0 8 256 1024 16 1 1\nseed 0 16 512 1024 8 1 2\n"
-                 "seed 0 4 256 1024 8 0 3\nseed 0 4 256 1024 8 0 -1\n")
+                 # the draw column: 1 (at pass start), 2 (kernel), 3 (lead workgroup); 4 and -1 are rejected
+                 "seed 0 8 256 1024 16 1 1\nseed 0 16 512 1024 8 1 2\nseed 0 32 512 1024 8 1 3\n"
+                 "seed 0 4 256 1024 8 0 4\nseed 0 4 256 1024 8 0 -1\n")
     try:
-        assert kl.lib().kmpp_tune_load(str(p).encode()) == 4
+        assert kl.lib().kmpp_tune_load(str(p).encode()) == 5
     finally:
         kl.lib().kmpp_tune_load(kl.TUNE_PATH.encode())  # the shipped table again

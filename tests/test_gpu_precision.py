@@ -78,25 +78,26 @@ def test_fp8_seed_parity(kl, d):
 
 @pytest.mark.parametrize("fmt,d", [("bf16", 32), ("bf16", 64), ("fp8", 64), ("fp8", 128)])
 def test_precision_forms_draw_placements(kl, fmt, d):
-    # the draw at the start of the next pass and the draw kernel at 256
-    # threads: the same seeds, D and recheck values, and both against the
-    # oracle on the dequantised rows
+    # the draw at the start of the next pass, the draw kernel and the lead
+    # workgroup's draw at 256 threads: the same seeds, D and recheck values,
+    # and against the oracle on the dequantised rows
     N, K = 60_013, 24
     Xh = kmpp_synth.gaussian(N, d, seed=400 + d, scale=5.0)
     X = Xh.cuda()
     dt = kl.KMPP_BF16 if fmt == "bf16" else kl.KMPP_FP8_E4M3
     q, e = kl.kmpp_quantize(X, dt)
     out = []
-    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL):
+    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL, kl.KMPP_DRAW_LEAD):
         rec = torch.zeros(2 * K, device="cuda")
         idx, C, D, st = run_seed(kl, X, K, seed=6, Xq=q, Xq_exp=e, dtype=dt, out_recheck=rec, threads=256,
                                  draw=draw)
         assert st == 0
         out.append((idx, C, D, rec.cpu().numpy()))
-    (ia, Ca, Da, ra), (ib, Cb, Db, rb) = out
-    assert np.array_equal(ia, ib)
-    assert np.array_equal(Da.view(np.uint32), Db.view(np.uint32))
-    assert np.array_equal(ra.view(np.uint32), rb.view(np.uint32))
+    ia, Ca, Da, ra = out[0]
+    for ib, Cb, Db, rb in out[1:]:
+        assert np.array_equal(ia, ib)
+        assert np.array_equal(Da.view(np.uint32), Db.view(np.uint32))
+        assert np.array_equal(ra.view(np.uint32), rb.view(np.uint32))
     if fmt == "bf16":
         Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
     else:

@@ -90,6 +90,62 @@ def test_draw_at_pass_start_matches_draw_kernel(kl, threads, rpt, K):
         check_seed_run(Xh.numpy(), K, 4, idx, C, D)
 
 
+@pytest.mark.parametrize("threads,rpt,K", [(256, 0, 24), (256, 64, 40), (512, 0, 24), (512, 512, 300),
+                                           (256, 5000, 24), (512, 16, 33)])
+def test_lead_draw_matches_other_placements(kl, threads, rpt, K):
+    # workgroup 0 of each pass drawing for all (in place, the others waiting
+    # for its index): the same fixed-order steps as the draw at pass start,
+    # so the same seeds and D at any size where that one runs, the draw
+    # kernel's at 256 threads, and the oracle's.  rpt=16 gives 7717 tiles
+    N, d = 123_457, 32
+    Xh = kmpp_synth.gaussian(N, d, seed=21)
+    X = Xh.cuda()
+    _say("lead draw vs other placements", N, d, K, threads, rpt)
+    a = run_seed(kl, X, K, seed=5, threads=threads, rows_per_tile=rpt, draw=kl.KMPP_DRAW_LEAD)
+    b = run_seed(kl, X, K, seed=5, threads=threads, rows_per_tile=rpt, draw=kl.KMPP_DRAW_KERNEL)
+    assert a[3] == 0 and b[3] == 0
+    if threads == 256:
+        assert np.array_equal(a[0], b[0])
+        assert np.array_equal(a[2], b[2])
+    if rpt not in (5000, 16):  # the draw at pass start runs (LDS share, tile count)
+        c = run_seed(kl, X, K, seed=5, threads=threads, rows_per_tile=rpt, draw=kl.KMPP_DRAW_PASS)
+        assert np.array_equal(a[0], c[0])
+        assert np.array_equal(a[2], c[2])
+    check_seed_run(Xh.numpy(), K, 5, a[0], a[1], a[2])
+
+
+def test_lead_draw_edge_cases_and_repeats(kl):
+    # a zero sum of D (uniform draws, warning), a NaN row (error), K=1, K=2,
+    # K=N, and back-to-back runs on one workspace (the published index is
+    # tagged by pass and reset by each run's first kernel)
+    L = kl.KMPP_DRAW_LEAD
+    Xh = torch.ones((1000, 8))
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 5, seed=2, draw=L)
+    assert st == kl.W_DEGENERATE
+    assert idx.tolist() == oracle.seed(Xh.numpy(), 5, seed=2).idx.tolist()
+    Xn = kmpp_synth.gaussian(1000, 8, seed=3)
+    Xn[17, 2] = float("nan")
+    assert run_seed(kl, Xn.cuda(), 5, seed=2, draw=L)[3] == kl.E_NONFINITE
+    Xg = kmpp_synth.gaussian(5000, 8, seed=13)
+    for K in (1, 2):
+        idx, C, D, st = run_seed(kl, Xg.cuda(), K, seed=K, draw=L)
+        assert st == 0
+        check_seed_run(Xg.numpy(), K, K, idx, C, D)
+    Xs = kmpp_synth.gaussian(300, 8, seed=14)
+    idx, C, D, st = run_seed(kl, Xs.cuda(), 300, seed=9, draw=L)
+    assert st == 0
+    assert sorted(idx.tolist()) == list(range(300))
+    N, d = 200_003, 32
+    Xr = kmpp_synth.gaussian(N, d, seed=22)
+    X = Xr.cuda()
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(N, d, 64), "cuda")
+    for K, seed in ((64, 1), (7, 2), (64, 1), (2, 4)):
+        _say("lead draw, repeat", K, seed)
+        idx, C, D, st = run_seed(kl, X, K, seed=seed, ws=ws, draw=L)
+        assert st == 0
+        check_seed_run(Xr.numpy(), K, seed, idx, C, D)
+
+
 def test_draw_at_pass_start_repeated_calls_one_workspace(kl):
     # the D and tile-sum buffers alternate by pass and the last pass writes
     # the caller's D whatever the parity of K: back-to-back runs on one
@@ -129,7 +185,7 @@ def test_draw_at_pass_start_edge_cases(kl):
     assert np.all(D == 0.0)
 
 
-@pytest.mark.parametrize("draw", ["pass", "kernel"])
+@pytest.mark.parametrize("draw", ["pass", "kernel", "lead"])
 def test_graph_capture_seed_and_assign(kl, draw):
     # seeding + assignment captured into a HIP graph and replayed three
     # times, outputs cleared eagerly between replays: every replay equals
@@ -138,7 +194,7 @@ def test_graph_capture_seed_and_assign(kl, draw):
     N, d, K = 150_001, 32, 40
     Xh = kmpp_synth.gaussian(N, d, seed=15)
     X = Xh.cuda()
-    dm = kl.KMPP_DRAW_PASS if draw == "pass" else kl.KMPP_DRAW_KERNEL
+    dm = {"pass": kl.KMPP_DRAW_PASS, "kernel": kl.KMPP_DRAW_KERNEL, "lead": kl.KMPP_DRAW_LEAD}[draw]
     idx = torch.empty(K, dtype=torch.int64, device="cuda")
     C = torch.empty((K, d), dtype=torch.float32, device="cuda")
     D = torch.empty(N, dtype=torch.float32, device="cuda")

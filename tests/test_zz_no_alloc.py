@@ -69,7 +69,7 @@ def test_two_calls_second_smaller(kl):
 def test_both_draw_placements_and_bf16(kl):
     Xh = kmpp_synth.gaussian(60_013, 64, seed=11, scale=3.0)
     X = Xh.cuda()
-    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL):
+    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_KERNEL, kl.KMPP_DRAW_LEAD):
         print("noalloc: gaussian 60013 x 64, draw", draw, flush=True)
         a = _noalloc(kl, X, 40, 5, draw=draw)
         _same(a, _with_ws(kl, X, 40, 5, draw=draw))
