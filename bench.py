@@ -602,14 +602,15 @@ ASSIGN_CASES = {
 def seed_only(kl, name, K):
     """Counter-collection driver: the calibration copy bench.py's main run
     makes (256 MiB read, 256 MiB written), then one seeding of the first K
-    seeds of the plain (1M x 32) or large (16.7M x 64) FP32 workload."""
+    seeds of the plain (1M x 32) or large (16.7M x 64) FP32 workload, with
+    the draws in their own kernel (the pass kernel the roofline times)."""
     import kmpp_synth
     cal = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
     torch.empty_like(cal).copy_(cal)
     del cal
     w = kmpp_synth.plain(device="cuda") if name == "plain" else kmpp_synth.large(device="cuda")
     torch.cuda.synchronize()
-    kl.kmpp_seed(w.X, min(K, w.K), 0)
+    kl.kmpp_seed(w.X, min(K, w.K), 0, draw=kl.KMPP_DRAW_KERNEL)
     torch.cuda.synchronize()
     print("seed-only done", name, w.N, w.d, min(K, w.K), flush=True)
 
