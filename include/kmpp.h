@@ -114,10 +114,11 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *                     launches per seed; D updated in place where it changed)
  *   KMPP_DRAW_LEAD    workgroup 0 of pass m+1 draws seed m at its start and
  *                     publishes the index; the pass's other workgroups wait
- *                     for it (bounded: KMPP_E_TIMEOUT after one second) with
- *                     their first rows in flight (one launch per seed; D and
- *                     tile sums in place).  Exact widths, unweighted seeding;
- *                     else KERNEL.
+ *                     for it (bounded: KMPP_E_TIMEOUT after one second, see
+ *                     kmpp_tune_load; narrow FP32 rows with their first rows
+ *                     already in flight).  One launch per seed, D and tile
+ *                     sums in place.  Exact widths, unweighted seeding; else
+ *                     KERNEL.
  */
 enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2, KMPP_DRAW_LEAD = 3 };
 
@@ -358,8 +359,11 @@ int kmpp_graph_destroy(kmpp_graph g);
  * alpha) set the batched planner's cost model; "batched wait_ms <v>" sets
  * the budget of one gang wait (v < 0: automatic, eight times the plan's
  * estimated length and at least one second; 0: every wait gives up at once,
- * which forces KMPP_E_TIMEOUT for testing).  Returns the number of entries
- * read or KMPP_E_INVALID. */
+ * which forces KMPP_E_TIMEOUT for testing); "lead wait_ms <v>" sets the
+ * budget of a pass's wait for the lead workgroup's index (KMPP_DRAW_LEAD;
+ * v < 0: one second, the default; 0: every wait gives up at once, which
+ * forces KMPP_E_TIMEOUT for testing).  Returns the number of entries read or
+ * KMPP_E_INVALID. */
 int kmpp_tune_load(const char* path);
 
 /*

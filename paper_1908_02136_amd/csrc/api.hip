@@ -28,6 +28,11 @@ struct SeedTune {
 };
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, SeedTune> g_tune;
+// budget of one wait for the lead workgroup's index, in ticks of the 100 MHz
+// real-time counter: one second unless the tuning table says otherwise
+// ("lead wait_ms <v>"; 0 makes every wait give up at once, for testing)
+constexpr uint64_t kLeadWaitDefault = 100000000ull;
+uint64_t g_lead_wait = kLeadWaitDefault;
 
 bool tuned(int dtype, int d, SeedTune* t) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -169,6 +174,10 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
   p.tag = tag;
   p.sumD = opts ? opts->out_sumD : nullptr;
   p.status_out = status_out;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    p.lead_wait = g_lead_wait;
+  }
   // the draw at pass start (unweighted seeding, exact-width passes): every
   // workgroup reads all tile sums, so their number is bounded, and its LDS
   // staging must leave the pass's occupancy alone (160 KiB of LDS per CU,
@@ -404,6 +413,10 @@ int kmpp_tune_load(const char* path) {
       ++n;
     } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "batched") == 0 &&
                batched_tune_set(key, val) == KMPP_OK) {
+      ++n;
+    } else if (sscanf(line, "%31s %31s %lf", kind, key, &val) == 3 && strcmp(kind, "lead") == 0 &&
+               strcmp(key, "wait_ms") == 0) {
+      g_lead_wait = val < 0.0 ? kLeadWaitDefault : (uint64_t)(val * 1e5);
       ++n;
     }
   }

@@ -38,6 +38,7 @@ struct SeedParams {
   double* tsum_w;        // draw at pass start: this pass's tile sums (tsum holds the previous pass's)
   double* sumD;          // [K] or null: the FP64 sum of D each draw inverted
   int32_t* status_out;   // or null: the status word, copied by the last pass
+  uint64_t lead_wait;    // lead-workgroup draw: budget of one wait in real-time counter ticks (0: give up at once)
 };
 
 // One compiled seed-pass kernel.

@@ -31,9 +31,6 @@
 
 namespace kmpp {
 
-// wait budget of the lead-workgroup draw: 1 s of the 100 MHz real-time counter
-constexpr uint64_t kLeadWaitTicks = 100000000ull;
-
 // ---------------------------------------------------------------- S1
 // First seed: i0 = min(floor(u_0 N), N-1); resets the status word.
 __global__ __launch_bounds__(256) void seed_init_kernel(SeedParams p) {
@@ -459,7 +456,8 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     // the index), and publishes the index tagged with the pass; the others
     // wait for it (their first rows already in flight).  Workgroup 0 is
     // dispatched first and waits for nobody, so every wait ends; a wait
-    // past its budget raises KMPP_E_TIMEOUT.
+    // past its budget (p.lead_wait ticks of the real-time counter; 0: none)
+    // raises KMPP_E_TIMEOUT and goes on with row 0.
     if (p.pass < 2) {
       cidx = p.idx[0];
     } else if (blockIdx.x == 0) {
@@ -470,10 +468,10 @@ __global__ __launch_bounds__(NT) void seed_pass_kernel(SeedParams p) {
     } else {
       if (tid == 0) {
         const uint64_t want = (uint64_t)(uint32_t)p.pass;
-        uint64_t v = __hip_atomic_load(&p.ctl->lead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t v = p.lead_wait ? __hip_atomic_load(&p.ctl->lead, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
         const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
         while ((v >> 32) != want) {
-          if (__builtin_amdgcn_s_memrealtime() - t0 > kLeadWaitTicks) {
+          if (p.lead_wait == 0 || __builtin_amdgcn_s_memrealtime() - t0 > p.lead_wait) {
             raise_status(p.ctl, KMPP_E_TIMEOUT);
             v = want << 32;
             break;

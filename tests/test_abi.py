@@ -98,8 +98,10 @@ def test_tune_file_parses(kl, tmp_path):
     p.write_text("seed 0 32 256 512\nseed 0 64 512 256\n# comment\nseed 9 1 256 1\nbogus\n"
                  # the draw column: 1 (at pass start), 2 (kernel), 3 (lead workgroup); 4 and -1 are rejected
                  "seed 0 8 256 1024 16 1 1\nseed 0 16 512 1024 8 1 2\nseed 0 32 512 1024 8 1 3\n"
-                 "seed 0 4 256 1024 8 0 4\nseed 0 4 256 1024 8 0 -1\n")
+                 "seed 0 4 256 1024 8 0 4\nseed 0 4 256 1024 8 0 -1\n"
+                 # the lead workgroup's wait budget
+                 "lead wait_ms 250\nlead budget 3\n")
     try:
-        assert kl.lib().kmpp_tune_load(str(p).encode()) == 5
+        assert kl.lib().kmpp_tune_load(str(p).encode()) == 6
     finally:
         kl.lib().kmpp_tune_load(kl.TUNE_PATH.encode())  # the shipped table again

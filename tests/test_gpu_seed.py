@@ -146,6 +146,30 @@ def test_lead_draw_edge_cases_and_repeats(kl):
         check_seed_run(Xr.numpy(), K, seed, idx, C, D)
 
 
+def test_lead_wait_expiry_reports_timeout(kl, tmp_path):
+    # the host sets a zero budget for the wait on the lead workgroup's index:
+    # every other workgroup gives up at once, the passes drain normally and
+    # the status says KMPP_E_TIMEOUT; with the default budget restored the
+    # same seeding is the oracle's again
+    N, d, K = 100_003, 32, 8
+    Xh = kmpp_synth.gaussian(N, d, seed=23)
+    X = Xh.cuda()
+    t0 = tmp_path / "lead0.txt"
+    t0.write_text("lead wait_ms 0\n")
+    t1 = tmp_path / "lead_default.txt"
+    t1.write_text("lead wait_ms -1\n")
+    try:
+        assert kl.kmpp_tune_load(str(t0)) == 1
+        _say("lead draw, zero wait budget", N, d, K)
+        st = run_seed(kl, X, K, seed=3, draw=kl.KMPP_DRAW_LEAD)[3]
+        assert st == kl.E_TIMEOUT
+    finally:
+        assert kl.kmpp_tune_load(str(t1)) == 1
+    idx, C, D, st = run_seed(kl, X, K, seed=3, draw=kl.KMPP_DRAW_LEAD)
+    assert st == 0
+    check_seed_run(Xh.numpy(), K, 3, idx, C, D)
+
+
 def test_draw_at_pass_start_repeated_calls_one_workspace(kl):
     # the D and tile-sum buffers alternate by pass and the last pass writes
     # the caller's D whatever the parity of K: back-to-back runs on one
