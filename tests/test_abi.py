@@ -101,7 +101,10 @@ def test_tune_file_parses(kl, tmp_path):
                  "seed 0 4 256 1024 8 0 4\nseed 0 4 256 1024 8 0 -1\n"
                  # the lead workgroup's wait budget
                  "lead wait_ms 250\nlead budget 3\n")
+    q = tmp_path / "lead_default.txt"
+    q.write_text("lead wait_ms -1\n")
     try:
         assert kl.lib().kmpp_tune_load(str(p).encode()) == 6
     finally:
         kl.lib().kmpp_tune_load(kl.TUNE_PATH.encode())  # the shipped table again
+        kl.lib().kmpp_tune_load(str(q).encode())        # and the default lead-wait budget
