@@ -51,7 +51,14 @@ struct AssignParams {
   int32_t Kq;           // K rounded up to 64
   int32_t* cflags;      // [N] the rows queued for the recheck (nflag of them)
   int32_t* qa;          // [N] BF16/FP8 rows: the rows the first stage queued for the second (nqueue)
+  uint64_t* pk;         // [kSplitCap] split recheck: (distance bits, index) minimum per queued row
 };
+
+// Queue positions below kSplitCap carry a 64-bit (distance, index) minimum
+// for the split recheck, which spreads the centres over workgroups while the
+// queue has fewer groups of rows than the recheck grid has workgroups.
+constexpr int kSplitCap = 65536;
+constexpr int kRecheckGrid = 2048;
 
 // ---- per-format row fragment handling
 template <int FMT>
@@ -699,7 +706,12 @@ void assign_mfma_kernel(AssignParams p) {
   int32_t* const queue = FIRST ? p.qa : p.cflags;
   if (tid == 0) s_base = s_nf ? (int)atomicAdd(counter, (uint32_t)s_nf) : 0;
   __syncthreads();
-  for (int i = tid; i < s_nf; i += 256) queue[s_base + i] = s_q[i];
+  for (int i = tid; i < s_nf; i += 256) {
+    queue[s_base + i] = s_q[i];
+    // the split recheck's minimum for this queue position starts above every
+    // (distance, index) pair
+    if (!FIRST && s_base + i < kSplitCap) p.pk[s_base + i] = ~0ull;
+  }
 }
 
 // ---------------------------------------------------------------- recheck
@@ -857,7 +869,24 @@ __global__ __launch_bounds__(256) void assign_recheck_kernel(AssignParams p) {
 // every centre value serves four rows.  Per thread, centres come in index
 // order (strict comparison keeps the smaller index), and the 32 lanes of a
 // half-wave are merged with ties to the smaller index.
+//
+// A short queue has fewer groups of rows than the grid has workgroups; the
+// centre tiles are then split into ranges, one work item per (group, range),
+// and each row's result is the minimum of its ranges' (distance bits,
+// index) pairs, taken with a 64-bit atomic minimum (distances are >= 0, so
+// their bit patterns order like the values; equal distances keep the
+// smaller index) and written out by assign_recheck_finish_kernel.
 constexpr int kTR = 32, kTC = 32, kTDMax = 128;
+constexpr int kMinTilesPerSplit = 2;
+
+// centre tiles per work item: all of them (no split) for long queues,
+// all-rows mode or a queue beyond the split slots
+__device__ __forceinline__ int recheck_tiles_per_item(int64_t n, int ntile, int all_rows) {
+  const int64_t groups = (n + kTR - 1) / kTR;
+  if (all_rows || groups == 0 || groups >= kRecheckGrid || n > kSplitCap) return ntile;
+  const int want = (int)((kRecheckGrid + groups - 1) / groups);  // ranges wanted per group
+  return max((ntile + want - 1) / want, min(kMinTilesPerSplit, ntile));
+}
 
 template <int FMT>
 __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams p) {
@@ -870,6 +899,9 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
   const int64_t n = p.all_rows ? p.N : (int64_t)p.ctl->nflag;
   const int64_t groups = (n + kTR - 1) / kTR;
   const int ntile = (p.K + kTC - 1) / kTC;            // Kq >= ntile * kTC (Kq is a multiple of 64)
+  const int tpi = recheck_tiles_per_item(n, ntile, p.all_rows);
+  const int splits = (ntile + tpi - 1) / tpi;
+  const int64_t items = groups * splits;
   const int tw = d * (kTC / 4);                       // 16-byte words of one centre tile
   const gptr<const char> ctb = as_global(reinterpret_cast<const char*>(p.Ct));
   float* xs = reinterpret_cast<float*>(xs4);
@@ -893,7 +925,9 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
       if (w < tw) cs4[b][w] = __builtin_bit_cast(float4, pre[i]);
     }
   };
-  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t g = it / splits;
+    const int t0 = (int)(it % splits) * tpi, t1 = min(ntile, t0 + tpi);
     // rows of the group (a short last group repeats its last row)
     for (int e = tid; e < d * kTR; e += 256) {
       const int k = e / kTR, r = e % kTR;
@@ -901,7 +935,7 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
       const int64_t row = p.all_rows ? i : (int64_t)p.cflags[i];
       xs[e] = x_at<FMT>(p, row, k);
     }
-    tload(0);
+    tload(t0);
     tstore(0);
     __syncthreads();
     float best[4];
@@ -911,9 +945,9 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
       best[r] = INFINITY;
       bi[r] = INT_MAX;
     }
-    for (int t = 0; t < ntile; ++t) {
-      if (t + 1 < ntile) tload(t + 1);
-      const float* cs = reinterpret_cast<const float*>(cs4[t & 1]);
+    for (int t = t0; t < t1; ++t) {
+      if (t + 1 < t1) tload(t + 1);
+      const float* cs = reinterpret_cast<const float*>(cs4[(t - t0) & 1]);
       float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
       for (int k = 0; k < d; ++k) {
@@ -933,7 +967,7 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
           best[r] = acc[r];
           bi[r] = j;
         }
-      if (t + 1 < ntile) tstore((t + 1) & 1);
+      if (t + 1 < t1) tstore((t + 1 - t0) & 1);
       __syncthreads();
     }
 #pragma unroll
@@ -951,13 +985,34 @@ __global__ __launch_bounds__(256) void assign_recheck_tiled_kernel(AssignParams 
       }
       const int64_t i = g * kTR + r0 + r;
       if (cj == 0 && i < n) {
-        const int64_t row = p.all_rows ? i : (int64_t)p.cflags[i];
-        // no comparable distance (NaN in the row or the centres): label -1
-        p.labels[row] = ib < p.K ? ib : -1;
-        if (p.mind) p.mind[row] = ib < p.K ? b : __builtin_nanf("");
+        if (splits == 1) {
+          const int64_t row = p.all_rows ? i : (int64_t)p.cflags[i];
+          // no comparable distance (NaN in the row or the centres): label -1
+          p.labels[row] = ib < p.K ? ib : -1;
+          if (p.mind) p.mind[row] = ib < p.K ? b : __builtin_nanf("");
+        } else {
+          // b is +inf or a distance >= 0 here (NaN never wins a comparison)
+          atomicMin(reinterpret_cast<unsigned long long*>(p.pk + i),
+                    ((unsigned long long)__float_as_uint(b) << 32) | (uint32_t)ib);
+        }
       }
     }
-    __syncthreads();  // the next group rewrites the row values
+    __syncthreads();  // the next item rewrites the row values
+  }
+}
+
+// The split recheck's results: the minimum pair of each queued row becomes
+// its label and distance (nothing to do when the queue was not split).
+__global__ __launch_bounds__(256) void assign_recheck_finish_kernel(AssignParams p) {
+  const int64_t n = p.all_rows ? p.N : (int64_t)p.ctl->nflag;
+  const int ntile = (p.K + kTC - 1) / kTC;
+  if (recheck_tiles_per_item(n, ntile, p.all_rows) >= ntile) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint64_t v = p.pk[i];
+    const int ib = (int)(uint32_t)v;
+    const int32_t row = p.cflags[i];
+    p.labels[row] = ib < p.K ? ib : -1;
+    if (p.mind) p.mind[row] = ib < p.K ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_nanf("");
   }
 }
 
@@ -1000,7 +1055,7 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 constexpr int64_t kSetupOneWg = 1 << 16;
 
 struct AssignLayout {
-  size_t cn, cmax, cp, ct, cflags, qa, total;
+  size_t cn, cmax, cp, ct, cflags, qa, pk, total;
   int Kp, dp, Kq;
 };
 
@@ -1034,6 +1089,8 @@ AssignLayout assign_layout(int64_t N, int d, int K, int dtype) {
   off += a256(sizeof(int32_t) * (size_t)N);
   L.qa = off;
   if (dtype != KMPP_F32) off += a256(sizeof(int32_t) * (size_t)N);
+  L.pk = off;
+  off += sizeof(uint64_t) * kSplitCap;
   L.total = off;
   return L;
 }
@@ -1052,10 +1109,11 @@ hipError_t launch_main(AssignParams& p, hipStream_t stream) {
 
 template <int FMT>
 void launch_recheck(const AssignParams& p, hipStream_t stream) {
-  const unsigned grid = 2048;
-  if (p.d <= kTDMax)
+  const unsigned grid = kRecheckGrid;
+  if (p.d <= kTDMax) {
     hipLaunchKernelGGL((assign_recheck_tiled_kernel<FMT>), dim3(grid), dim3(256), 0, stream, p);
-  else if (p.d <= kRecheckLdsD)
+    hipLaunchKernelGGL(assign_recheck_finish_kernel, dim3(kSplitCap / 256), dim3(256), 0, stream, p);
+  } else if (p.d <= kRecheckLdsD)
     hipLaunchKernelGGL((assign_recheck_kernel<FMT, true>), dim3(grid), dim3(256), 0, stream, p);
   else
     hipLaunchKernelGGL((assign_recheck_kernel<FMT, false>), dim3(grid), dim3(256), 0, stream, p);
@@ -1115,6 +1173,7 @@ int launch_assign(const void* X, const int8_t* X_exp, int dtype, const float* C,
   p.Kq = L.Kq;
   p.cflags = reinterpret_cast<int32_t*>(w + L.cflags);
   p.qa = reinterpret_cast<int32_t*>(w + L.qa);
+  p.pk = reinterpret_cast<uint64_t*>(w + L.pk);
 
   p.all_rows = 0;
 

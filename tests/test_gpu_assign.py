@@ -139,11 +139,13 @@ def test_unitsphere_bf16_sample(kl):
     check_assign(Xd, C.cpu().numpy(), lab, mind)
 
 
+@pytest.mark.parametrize("K", [20, 300])
 @pytest.mark.parametrize("d", [8, 32, 300])
-def test_nan_row_gets_label_minus_one(kl, d):
+def test_nan_row_gets_label_minus_one(kl, d, K):
     # a row with a NaN has no comparable distance: label -1, distance NaN;
-    # every other row is unaffected
-    N, K = 3000, 20
+    # every other row is unaffected (K = 300 spreads a short recheck queue's
+    # centre tiles over several workgroups for d <= 128)
+    N = 3000
     Xh = kmpp_synth.gaussian(N, d, seed=77 + d)
     Ch = Xh[:K].clone()
     Xh[123, d // 2] = float("nan")
@@ -187,6 +189,33 @@ def test_recheck_queue_short_and_long(kl, N):
     print("assign recheck queue", N, flush=True)
     lab, mind = run_assign(kl, Xh.cuda(), Ch.cuda())
     check_assign(Xh.numpy(), Ch.numpy(), lab, mind)
+
+
+@pytest.mark.parametrize("d", [16, 64])
+def test_short_recheck_queue_ties_and_nan(kl, d):
+    # every row goes to the recheck (all near one far point), and the queue
+    # is short enough for its centre tiles to be split over workgroups: the
+    # second half of the centres repeats the first, so each row's best
+    # distance is reached in two different tile ranges and the smaller index
+    # must win; a NaN row still gets label -1
+    N, K = 5_003, 320
+    g = torch.Generator().manual_seed(d)
+    Ch = (500.0 + torch.randn((K // 2, d), generator=g)).float()
+    Ch = torch.cat([Ch, Ch]).contiguous()
+    Xh = (500.0 + torch.randn((N, d), generator=g)).float()
+    Xh[4_321, 3] = float("nan")
+    print("assign short recheck queue ties", d, flush=True)
+    for out_mind in (None, False):
+        lab, mind, _ = kl.kmpp_assign(Xh.cuda(), Ch.cuda(), out_mind=out_mind)
+        torch.cuda.synchronize()
+        lab = lab.cpu().numpy()
+        assert lab[4_321] == -1
+        keep = np.arange(N) != 4_321
+        assert np.all((lab[keep] >= 0) & (lab[keep] < K // 2))
+        if mind is not None:
+            mind = mind.cpu().numpy()
+            assert np.isnan(mind[4_321])
+            check_assign(Xh.numpy()[keep], Ch.numpy(), lab[keep], mind[keep])
 
 
 @pytest.mark.parametrize("dtype", [0, 1, 2])
