@@ -42,7 +42,9 @@ struct AssignParams {
   Ctl* ctl;             // status; nflag counts the rows queued for the recheck
   int32_t* labels;
   float* mind;
-  float* cmax2;         // max_j ||c_j||^2 (workspace scalar)
+  float* cmax2;         // [3] workspace scalars: max_j ||c_j||^2, and (BF16 / FP8 rows)
+                        // max_j ||c_j - hi_j||^2, max_j ||c_j - hi_j - lo_j||^2 (the
+                        // residuals of the high part and of both parts)
   int64_t N;
   int32_t d, K, Kp, dp; // dp = padded d: 4 * VPL * (steps per tile)
   int32_t nblk;         // number of 16-row blocks
@@ -172,31 +174,58 @@ __device__ __forceinline__ void strided_batched(I tid, I stride, I total, V&& va
   for (I e = full + tid; e < total; e += stride) out(e, val(e));
 }
 
+// BF16 high part (round to nearest even) of c and BF16 remainder of c - hi
+// (c - hi is exact in FP32), as 16-bit patterns.
+__device__ __forceinline__ void split_bf16(float c, uint32_t& hi, uint32_t& lo) {
+  const uint32_t hb = __float_as_uint(c);
+  hi = ((hb + 0x7FFFu + ((hb >> 16) & 1u)) >> 16) & 0xFFFFu;
+  const uint32_t rb = __float_as_uint(c - __uint_as_float(hi << 16));
+  lo = ((rb + 0x7FFFu + ((rb >> 16) & 1u)) >> 16) & 0xFFFFu;
+}
+
 // A thread takes items tid, tid + stride, ...; it returns the bits of the
-// largest ||c_j||^2 it saw (as unsigned integers non-negative floats order
-// like their values, and NaN above them).
+// largest ||c_j||^2 it saw and (BF16 / FP8 rows) of the largest squared
+// residuals ||c_j - hi_j||^2 and ||c_j - hi_j - lo_j||^2 (as unsigned
+// integers non-negative floats order like their values, and NaN above
+// them).
 // I: the index type (32-bit when every index fits, so the divisions below
 // stay short and branch-free).
 template <typename I>
-__device__ uint32_t prep_part(const AssignParams& p, int fmt, I tid, I stride) {
+__device__ uint3 prep_part(const AssignParams& p, int fmt, I tid, I stride) {
   const int Kt = p.Kp / 16;
   const int DQ = p.dp / 4;
-  uint32_t mx = 0u;
+  uint3 mx = make_uint3(0u, 0u, 0u);
   for (I j = tid; j < p.Kp; j += stride) {
     // ||c||^2 summed over k in order in FP64 and rounded once, so each chain
     // start carries a single FP32 rounding (at most 2^-25 ||c||^2), which the
-    // error bound's slack covers; an FP32 sum would add up to d 2^-24 ||c||^2
-    double a = 0.0;
+    // error bound's slack covers; an FP32 sum would add up to d 2^-24 ||c||^2.
+    // The residuals c - hi and c - hi - lo are exact in FP32 and their
+    // squares are summed the same way.
+    double a = 0.0, r1 = 0.0, r2 = 0.0;
     for (int k0 = 0; k0 < p.d; k0 += kPrepU) {
       float c[kPrepU];
 #pragma unroll
       for (int u = 0; u < kPrepU; ++u) c[u] = c_at(p, j, k0 + u);
 #pragma unroll
-      for (int u = 0; u < kPrepU; ++u) a = fma((double)c[u], (double)c[u], a);  // +0 past d: a unchanged
+      for (int u = 0; u < kPrepU; ++u) {
+        a = fma((double)c[u], (double)c[u], a);  // +0 past d: a unchanged
+        if (fmt != FMT_F32) {
+          uint32_t hi, lo;
+          split_bf16(c[u], hi, lo);
+          const float e1 = c[u] - __uint_as_float(hi << 16);
+          const float e2 = e1 - __uint_as_float(lo << 16);
+          r1 = fma((double)e1, (double)e1, r1);
+          r2 = fma((double)e2, (double)e2, r2);
+        }
+      }
     }
     const float af = (float)a;
     p.cn[j] = j < p.K ? -0.5f * af : -INFINITY;  // exact scaling
-    if (j < p.K) mx = max(mx, __float_as_uint(af));
+    if (j < p.K) {
+      mx.x = max(mx.x, __float_as_uint(af));
+      mx.y = max(mx.y, __float_as_uint((float)r1));
+      mx.z = max(mx.z, __float_as_uint((float)r2));
+    }
   }
   if (fmt == FMT_F32) {
     float* Cp = (float*)const_cast<void*>(p.Cp);
@@ -222,11 +251,8 @@ __device__ uint32_t prep_part(const AssignParams& p, int fmt, I tid, I stride) {
           return c_at(p, 16 * jt + lane % 16, (lane / 16) * DQ + 8 * s + t);
         },
         [&](I e, float c) {
-          const uint32_t hb = __float_as_uint(c);
-          const uint32_t hi = ((hb + 0x7FFFu + ((hb >> 16) & 1u)) >> 16) & 0xFFFFu;  // RNE
-          const float rem = c - __uint_as_float(hi << 16);                              // exact
-          const uint32_t rb = __float_as_uint(rem);
-          const uint32_t lo = ((rb + 0x7FFFu + ((rb >> 16) & 1u)) >> 16) & 0xFFFFu;
+          uint32_t hi, lo;
+          split_bf16(c, hi, lo);
           Cp[e] = (uint16_t)((e / 512 / S) % 2 == 0 ? hi : lo);  // part 0 high, 1 remainder
         });
   }
@@ -234,9 +260,12 @@ __device__ uint32_t prep_part(const AssignParams& p, int fmt, I tid, I stride) {
 }
 
 __global__ __launch_bounds__(256) void assign_prep_kernel(AssignParams p, int fmt) {
-  const uint32_t mx =
+  const uint3 mx =
       prep_part<int64_t>(p, fmt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
-  if (mx) atomicMax(reinterpret_cast<unsigned int*>(p.cmax2), mx);
+  unsigned int* const m = reinterpret_cast<unsigned int*>(p.cmax2);
+  if (mx.x) atomicMax(m, mx.x);
+  if (mx.y) atomicMax(m + 1, mx.y);
+  if (mx.z) atomicMax(m + 2, mx.z);
 }
 
 // ---------------------------------------------------------------- main
@@ -266,10 +295,11 @@ constexpr int assign_min_waves(int fmt, int dqk) {
 //
 // BF16 / FP8 rows run in two stages (NP, the centre parts taken):
 //   NP = 1: every row, products with the centres' BF16 high parts only (half
-//           the matrix work); the bound adds the high part's rounding, at
-//           most 2^-9 |x_k c_k| per term; rows not decided go to queue qa;
+//           the matrix work); the bound adds 2 |x| max_j |c_j - hi_j|;
+//           rows not decided go to queue qa;
 //   NP = 2: only the rows in qa (gathered), products with both parts, the
-//           tight bound; rows not decided go to the recheck queue.
+//           bound adding 2 |x| max_j |c_j - hi_j - lo_j|; rows not decided
+//           go to the recheck queue.
 // FP32 rows take one stage (NP = 1, the FP32 product, tight bound).
 template <int FMT, int DQK, int RB, int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(assign_min_waves(FMT, DQK))))
@@ -607,8 +637,11 @@ void assign_mfma_kernel(AssignParams p) {
   // the row (the row values are the fragments in registers, exact) and are
   // summed over the four lane groups, so the branches around them are taken
   // by whole waves.
-  const float cmax2 = *p.cmax2;
+  const float cmax2 = p.cmax2[0];
   const float cmax = sqrtf(cmax2);
+  // the centres' residual left out of the products: c - hi (first stage)
+  // or c - hi - lo (second stage), its largest norm
+  const float rmax = BF ? sqrtf(p.cmax2[FIRST ? 1 : 2]) : 0.0f;
   constexpr float kGrowth = 1.05f;
   constexpr int QV = F::VPL * S;  // values per lane quarter (= DQ)
 #pragma unroll
@@ -619,13 +652,18 @@ void assign_mfma_kernel(AssignParams p) {
     const int64_t row = rowv[rb];
     const float xn = sqrtf(x2) * 1.0001f;
     const float mag = cmax2 + 2.0f * xn * cmax;
-    // score error bound: FP32 accumulation over the products and the chain
-    // start, plus (BF16 / FP8, NP = 2) the remainder part's rounding 2^-17
-    // |x||c| or (NP = 1) the high part's rounding 2^-9 |x||c|, doubled
+    // E bounds the error of the difference of two t values (mag = max|c|^2
+    // + 2 |x| max|c| spans both chains): FP32 accumulation over the
+    // products and the chain start, (dp + 8) 2^-24 mag (2 dp products for
+    // both centre parts; products of BF16 values are exact), plus, for
+    // BF16 / FP8 rows, the centre residual r_j that the products leave out:
+    // |<x, r_j>| <= |x| |r_j| per value, 2 |x| max|r| for a difference.
+    // (Per value, the worst case is 2^-8 |c_k| for the high part, rounded to
+    // 8 significant bits, and 2^-16 |c_k| for both parts; residual norms
+    // are typically well under that.)
     const float unit = (FMT == FMT_F32 || NP == 1) ? (float)(p.dp + 8) * 0x1p-24f
-                                                   : (float)(2 * p.dp + 8) * 0x1p-24f + 0x1p-16f;
-    float E = unit * mag * kGrowth;
-    if constexpr (FIRST) E += 0x1p-8f * xn * cmax * kGrowth;
+                                                   : (float)(2 * p.dp + 8) * 0x1p-24f;
+    const float E = (unit * mag + 2.0f * xn * rmax) * kGrowth;
     // t values: score gaps are twice the t gaps
     const bool sure_a = 2.0f * (b1[rb] - oa[rb]) > 2.0f * E && bj[rb] < p.K;
     const bool sure_t = 2.0f * (b1[rb] - ot[rb]) > 2.0f * E && bj[rb] < p.K;
@@ -1020,13 +1058,15 @@ __global__ void assign_reset_kernel(Ctl* ctl, float* cmax2) {
   ctl->status = KMPP_OK;
   ctl->nflag = 0u;
   ctl->nqueue = 0u;
-  *cmax2 = 0.0f;
+  cmax2[0] = 0.0f;
+  cmax2[1] = 0.0f;
+  cmax2[2] = 0.0f;
 }
 
 // Small centre sets: the reset, the transposed copy, the chain starts and
 // the packed fragments in one workgroup (one launch instead of three).
 __global__ __launch_bounds__(1024) void assign_setup_kernel(AssignParams p, int fmt) {
-  __shared__ uint32_t smx[16];
+  __shared__ uint3 smx[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     p.ctl->status = KMPP_OK;
@@ -1035,15 +1075,26 @@ __global__ __launch_bounds__(1024) void assign_setup_kernel(AssignParams p, int 
   }
   // every index fits 32 bits here (Kp * dp <= 65536, d <= 256)
   transpose_part<uint32_t>(p, (uint32_t)tid, 1024u);
-  uint32_t mx = prep_part<uint32_t>(p, fmt, (uint32_t)tid, 1024u);
+  uint3 mx = prep_part<uint32_t>(p, fmt, (uint32_t)tid, 1024u);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  for (int o = 32; o > 0; o >>= 1) {
+    mx.x = max(mx.x, (uint32_t)__shfl_xor((int)mx.x, o, 64));
+    mx.y = max(mx.y, (uint32_t)__shfl_xor((int)mx.y, o, 64));
+    mx.z = max(mx.z, (uint32_t)__shfl_xor((int)mx.z, o, 64));
+  }
   if (lane == 0) smx[wave] = mx;
   __syncthreads();
   if (tid == 0) {
-    uint32_t m = 0u;
-    for (int w = 0; w < 16; ++w) m = max(m, smx[w]);
-    *reinterpret_cast<uint32_t*>(p.cmax2) = m;
+    uint3 m = make_uint3(0u, 0u, 0u);
+    for (int w = 0; w < 16; ++w) {
+      m.x = max(m.x, smx[w].x);
+      m.y = max(m.y, smx[w].y);
+      m.z = max(m.z, smx[w].z);
+    }
+    uint32_t* const o = reinterpret_cast<uint32_t*>(p.cmax2);
+    o[0] = m.x;
+    o[1] = m.y;
+    o[2] = m.z;
   }
 }
 

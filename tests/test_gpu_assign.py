@@ -191,6 +191,38 @@ def test_recheck_queue_short_and_long(kl, N):
     check_assign(Xh.numpy(), Ch.numpy(), lab, mind)
 
 
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("d", [64, 128])
+def test_first_stage_bound_covers_high_part_rounding(kl, dtype, d):
+    # Rounding a centre value to its BF16 high part (8 significant bits,
+    # nearest even) can move it by 2^-8 of itself, so the first stage's
+    # products can misjudge the gap between two centres by 2^-7 |x| max|c|.
+    # Rows of ones; centre 0 has every value at 1 + 3 * 2^-8 (its high part
+    # rounds up, to 1 + 2^-6), centre 5 at 1 + 2^-8 (rounds down, to 1), so
+    # the high parts rank centre 0 first by about d / 128 in t while centre 5
+    # is nine times nearer; a bound of 2^-8 |x| max|c| would decide the rows
+    # for centre 0.  The other centres have centre 0's norm (the bound grows
+    # with max|c|) and random signs, so they sit far from the rows of ones;
+    # the other rows are Gaussian.
+    K, N = 20, 3_000
+    u = 2.0 ** -8
+    g = torch.Generator().manual_seed(d + dtype)
+    C = (1 + 3 * u) * torch.sign(torch.randn((K, d), generator=g) + 0.5)
+    C[0] = 1 + 3 * u
+    C[5] = 1 + u
+    Xh = torch.randn((N, d), generator=g) * 3.0
+    Xh[:1_000] = 1.0
+    X, E = kl.kmpp_quantize(Xh.cuda(), dtype)
+    print("assign first-stage bound", dtype, d, flush=True)
+    lab, mind = run_assign(kl, X, C.float().cuda(), X_exp=E, dtype=dtype)
+    assert np.all(lab[:1_000] == 5), np.unique(lab[:1_000])
+    if dtype == 1:
+        Xd = oracle.bf16_decode(oracle.bf16_encode(Xh.numpy()))
+    else:
+        Xd = oracle.fp8_dequantize_rows(*oracle.fp8_quantize_rows(Xh.numpy()))
+    check_assign(Xd, C.float().numpy(), lab, mind)
+
+
 @pytest.mark.parametrize("d", [16, 64])
 def test_short_recheck_queue_ties_and_nan(kl, d):
     # every row goes to the recheck (all near one far point), and the queue
