@@ -166,10 +166,33 @@ def batched_form(kl, reps):
     nk = sum(n * k for n, k in zip(spec.N, spec.K))
     xb = sum(n * d * 4 * k for n, d, k in zip(spec.N, spec.d, spec.K))
     _log(f"  batched: {ms:.2f} ms (status {st}), 512 plain calls {pms:.2f} ms")
-    return {"workload": "512 instances, N log-uniform [1e3,2e5], d in {8,16,64}, K uniform [8,256]",
-            "batched_ms": ms, "plain_calls_ms": pms, "speedup_vs_plain": pms / ms, "status": st,
-            "dists_per_s": nk / (ms * 1e-3), "GBps": xb / (ms * 1e-3) / 1e9,
-            "frac_hbm": xb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res = {"workload": "512 instances, N log-uniform [1e3,2e5], d in {8,16,64}, K uniform [8,256]",
+           "batched_ms": ms, "plain_calls_ms": pms, "speedup_vs_plain": pms / ms, "status": st,
+           "dists_per_s": nk / (ms * 1e-3), "GBps": xb / (ms * 1e-3) / 1e9,
+           "frac_hbm": xb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del pouts, pws
+    # the same batch streaming BF16 / FP8 rows (one graph launch each)
+    for tag, dt in (("bf16", kl.KMPP_BF16), ("fp8", kl.KMPP_FP8_E4M3)):
+        Q = [kl.kmpp_quantize(X, dt) for X in Xs]
+        qouts, qws = kl.kmpp_seed_batched_prepare(Xs, spec.K, 0, dtype=dt, Xq=[q for q, _ in Q],
+                                                  Xq_exp=[e for _, e in Q] if dt == kl.KMPP_FP8_E4M3 else None)
+        qg = kl.Graph()
+        with torch.cuda.stream(s):
+            with qg.capture():
+                kl.kmpp_seed_batched_launch(qws)
+        qg.launch(s)
+        s.synchronize()
+        qms = time_events(lambda: qg.launch(s), reps, stream=s)
+        qst = kl.kmpp_status(qws, stream=s)
+        eb = 2 if dt == kl.KMPP_BF16 else 1
+        qb = sum(n * d * eb * k for n, d, k in zip(spec.N, spec.d, spec.K))
+        _log(f"  batched {tag}: {qms:.2f} ms (status {qst})")
+        res[f"{tag}_ms"] = qms
+        res[f"{tag}_status"] = qst
+        res[f"{tag}_speedup_vs_f32"] = ms / qms
+        res[f"{tag}_GBps"] = qb / (qms * 1e-3) / 1e9
+        del Q, qouts, qws, qg
+    return res
 
 
 def lloyd_iterations(kl, name, w, iters=5, reps=2, dtype=0):

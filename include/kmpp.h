@@ -299,7 +299,11 @@ int kmpp_lloyd(const void* X, const int8_t* X_exp, int32_t dtype, int64_t N, int
 int kmpp_quantize(const float* X, int64_t N, int32_t d, int32_t dtype, void* Xq, int8_t* Xq_exp,
                   void* stream);
 
-/* One independent seeding instance of the batched form. */
+/* One independent seeding instance of the batched form.  The last three
+ * fields choose the rows the passes stream, as kmpp_seed's dtype, Xq and
+ * Xq_exp do (zero / NULL: the FP32 rows X); the centres are always the
+ * original FP32 rows of X, and with BF16 / FP8 rows each drawn row's D is
+ * set to 0. */
 typedef struct kmpp_instance {
   const float* X;       /* FP32 [N, d], 16-byte aligned */
   int64_t N;
@@ -308,6 +312,9 @@ typedef struct kmpp_instance {
   float* out_centers;   /* FP32 [K, d] */
   float* out_D;         /* FP32 [N] or NULL */
   int64_t* out_idx;     /* int64 [K] or NULL */
+  int32_t dtype;        /* KMPP_F32, KMPP_BF16 or KMPP_FP8_E4M3 */
+  const void* Xq;       /* BF16 / FP8 rows [N, d] (kmpp_quantize), 16-byte aligned, or NULL for KMPP_F32 */
+  const int8_t* Xq_exp; /* FP8 row exponents [N], or NULL */
 } kmpp_instance;
 
 /*
@@ -341,6 +348,11 @@ int kmpp_seed_batched(const kmpp_instance* inst, int32_t n_inst, uint64_t seed, 
  * kmpp_seed_batched, kmpp_lloyd or kmpp_seed_parallel) into *out.  Returns
  * KMPP_OK or KMPP_E_HIP. */
 int kmpp_status(const void* workspace, void* stream, int32_t* out);
+/* The same word without synchronising any stream, for a caller that has
+ * already waited for the work that wrote it (the copy itself is a plain
+ * blocking device-to-host copy).  Returns KMPP_OK, KMPP_E_INVALID or
+ * KMPP_E_HIP. */
+int kmpp_status_poll(const void* workspace, int32_t* out);
 
 /* Graph capture helpers: capture the work a sequence of calls enqueues on
  * `stream` into an executable HIP graph and replay it.  The captured calls

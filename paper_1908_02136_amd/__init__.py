@@ -42,7 +42,7 @@ SYMBOLS = NOALLOC_SYMBOLS + [
     "kmpp_lloyd_workspace_bytes", "kmpp_lloyd", "kmpp_seed_parallel_capacity",
     "kmpp_seed_parallel_workspace_bytes", "kmpp_seed_parallel",
     "kmpp_batched_workspace_bytes", "kmpp_seed_batched_prepare", "kmpp_seed_batched_launch",
-    "kmpp_seed_batched", "kmpp_status", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
+    "kmpp_seed_batched", "kmpp_status", "kmpp_status_poll", "kmpp_graph_begin", "kmpp_graph_end", "kmpp_graph_launch",
     "kmpp_graph_destroy", "kmpp_tune_load", "kmpp_read_probe", "kmpp_strerror", "kmpp_version",
 ]
 
@@ -62,7 +62,8 @@ class SeedOpts(ctypes.Structure):
 
 class Instance(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("N", ctypes.c_int64), ("d", ctypes.c_int32), ("K", ctypes.c_int32),
-                ("out_centers", ctypes.c_void_p), ("out_D", ctypes.c_void_p), ("out_idx", ctypes.c_void_p)]
+                ("out_centers", ctypes.c_void_p), ("out_D", ctypes.c_void_p), ("out_idx", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32), ("Xq", ctypes.c_void_p), ("Xq_exp", ctypes.c_void_p)]
 
 
 _lib = None
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.kmpp_seed_batched.restype = ctypes.c_int
     L.kmpp_status.argtypes = [P, P, ctypes.POINTER(i32)]
     L.kmpp_status.restype = ctypes.c_int
+    L.kmpp_status_poll.argtypes = [P, ctypes.POINTER(i32)]
+    L.kmpp_status_poll.restype = ctypes.c_int
     L.kmpp_graph_begin.argtypes = [P]
     L.kmpp_graph_begin.restype = ctypes.c_int
     L.kmpp_graph_end.argtypes = [P, ctypes.POINTER(P)]
@@ -314,6 +317,14 @@ def kmpp_status(ws: torch.Tensor, stream=None) -> int:
     return int(out.value)
 
 
+def kmpp_status_poll(ws: torch.Tensor) -> int:
+    """The status word, read without synchronising a stream: call it after
+    waiting for the work that wrote it (e.g. torch.cuda.synchronize())."""
+    out = ctypes.c_int32(0)
+    _check(lib().kmpp_status_poll(_ptr(ws), ctypes.byref(out)), "kmpp_status_poll")
+    return int(out.value)
+
+
 # ---------------------------------------------------------------- formats
 def kmpp_quantize(X: torch.Tensor, dtype: int, stream=None):
     """Returns (Xq, Xq_exp): torch.bfloat16 [N, d] (exp None) or torch.float8_e4m3fn
@@ -424,9 +435,14 @@ def kmpp_lloyd(X: torch.Tensor, C: torch.Tensor, iters: int, *, X_exp=None, dtyp
 
 
 # ---------------------------------------------------------------- batched
-def _instances(Xs, Ks, outs):
+def _instances(Xs, Ks, outs, dtype=KMPP_F32, Xqs=None, Xq_exps=None):
     if len(Xs) != len(Ks) or len(Xs) != len(outs):
         raise ValueError("one K and one output triple per instance")
+    _check_dtype(dtype)
+    if dtype != KMPP_F32 and (Xqs is None or len(Xqs) != len(Xs)):
+        raise ValueError("BF16 / FP8 batches need one stored-row tensor per instance (Xq)")
+    if dtype == KMPP_FP8_E4M3 and (Xq_exps is None or len(Xq_exps) != len(Xs)):
+        raise ValueError("FP8 batches need one row-exponent tensor per instance (Xq_exp)")
     arr = (Instance * len(Xs))()
     for b, (X, K, (C, D, I)) in enumerate(zip(Xs, Ks, outs)):
         N, d = _rows(X, f"Xs[{b}]")
@@ -434,18 +450,28 @@ def _instances(Xs, Ks, outs):
         _expect(C, f"outs[{b}][0]", dtype=torch.float32, numel=K * d, required=False)
         _expect(D, f"outs[{b}][1]", dtype=torch.float32, numel=N, required=False)
         _expect(I, f"outs[{b}][2]", dtype=torch.int64, numel=K, required=False)
+        q = e = None
+        if dtype != KMPP_F32:
+            q = Xqs[b]
+            e = Xq_exps[b] if dtype == KMPP_FP8_E4M3 else None
+            if _check_rows(q, e, dtype, f"Xq[{b}]") != (N, d):
+                raise ValueError(f"Xq[{b}] must have the shape of Xs[{b}]")
         arr[b] = Instance(X.data_ptr(), X.shape[0], X.shape[1], K, None if C is None else C.data_ptr(),
-                          None if D is None else D.data_ptr(), None if I is None else I.data_ptr())
+                          None if D is None else D.data_ptr(), None if I is None else I.data_ptr(),
+                          dtype, None if q is None else q.data_ptr(), None if e is None else e.data_ptr())
     return arr
 
 
-def kmpp_batched_workspace_bytes(Xs, Ks) -> int:
+def kmpp_batched_workspace_bytes(Xs, Ks, *, dtype=KMPP_F32, Xq=None, Xq_exp=None) -> int:
     outs = [(None, None, None) for _ in Xs]  # output pointers are not read for sizing
-    return int(lib().kmpp_batched_workspace_bytes(_instances(Xs, Ks, outs), len(Xs)))
+    return int(lib().kmpp_batched_workspace_bytes(_instances(Xs, Ks, outs, dtype, Xq, Xq_exp), len(Xs)))
 
 
-def kmpp_seed_batched_prepare(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stream=None):
-    """Plan and upload a batch.  Returns (outs, ws) with outs[b] = (centers, D, idx)."""
+def kmpp_seed_batched_prepare(Xs, Ks, seed: int = 0, *, dtype=KMPP_F32, Xq=None, Xq_exp=None, outs=None, ws=None,
+                              stream=None):
+    """Plan and upload a batch.  Returns (outs, ws) with outs[b] = (centers, D, idx).
+    dtype, Xq (list of stored rows, kmpp_quantize) and Xq_exp (FP8 row
+    exponents) choose the rows the passes stream; one dtype per batch."""
     if len(Xs) < 1:
         raise ValueError("at least one instance")
     dev = Xs[0].device
@@ -453,8 +479,12 @@ def kmpp_seed_batched_prepare(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stre
         outs = [(torch.empty((K, X.shape[1]), dtype=torch.float32, device=dev),
                  torch.empty(X.shape[0], dtype=torch.float32, device=dev),
                  torch.empty(K, dtype=torch.int64, device=dev)) for X, K in zip(Xs, Ks)]
-    arr = _instances(Xs, Ks, outs)
+    arr = _instances(Xs, Ks, outs, dtype, Xq, Xq_exp)
     _require_cuda(*Xs)
+    if Xq is not None:
+        _require_cuda(*Xq)
+    if Xq_exp is not None:
+        _require_cuda(*Xq_exp)
     for o in outs:
         _require_cuda(*o)
     if ws is None:
@@ -468,8 +498,10 @@ def kmpp_seed_batched_launch(ws: torch.Tensor, stream=None):
     _check(lib().kmpp_seed_batched_launch(_ptr(ws), _stream(stream)), "kmpp_seed_batched_launch")
 
 
-def kmpp_seed_batched(Xs, Ks, seed: int = 0, *, outs=None, ws=None, stream=None):
-    outs, ws = kmpp_seed_batched_prepare(Xs, Ks, seed, outs=outs, ws=ws, stream=stream)
+def kmpp_seed_batched(Xs, Ks, seed: int = 0, *, dtype=KMPP_F32, Xq=None, Xq_exp=None, outs=None, ws=None,
+                      stream=None):
+    outs, ws = kmpp_seed_batched_prepare(Xs, Ks, seed, dtype=dtype, Xq=Xq, Xq_exp=Xq_exp, outs=outs, ws=ws,
+                                         stream=stream)
     kmpp_seed_batched_launch(ws, stream=stream)
     return outs, ws
 

@@ -350,6 +350,12 @@ int kmpp_status(const void* workspace, void* stream, int32_t* out) {
   return KMPP_OK;
 }
 
+int kmpp_status_poll(const void* workspace, int32_t* out) {
+  if (!workspace || !out) return KMPP_E_INVALID;
+  if (hipMemcpy(out, workspace, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return KMPP_E_HIP;
+  return KMPP_OK;
+}
+
 struct kmpp_graph_s {
   hipGraph_t graph;
   hipGraphExec_t exec;

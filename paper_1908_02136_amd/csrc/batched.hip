@@ -45,7 +45,9 @@ constexpr int kBIT = 4;             // wave iterations per block
 constexpr int kBMaxGang = 64;
 
 struct BInst {
-  const float* X;
+  const float* X;      // FP32 rows: the centres
+  const void* xs;      // the rows the passes stream (X, or BF16 / FP8 rows)
+  const int8_t* xexp;  // FP8 row exponents
   float* C;
   float* D;
   int64_t* idx;
@@ -70,6 +72,7 @@ struct BPlan {
   uint64_t seed;
   uint64_t wait_ticks;   // budget of one gang wait in real-time counter ticks; 0: give up at once
   int32_t n_inst, W, n_mslots;
+  int32_t fmt;           // the row format of every instance
 };
 
 __device__ __forceinline__ uint64_t tag16(int m) { return 0x8000u | ((uint32_t)m & 0x7FFFu); }
@@ -155,9 +158,9 @@ __device__ __forceinline__ int2 bminmax(int a, int b, int2* sh) {
   return r;
 }
 
-template <int CB, int G, int CPL, int U, bool FULL>
+template <int FMT, int CB, int G, int CPL, int U, bool FULL>
 __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared& S) {
-  using St = Streamer<FMT_F32, CB, G, CPL, U, FULL, kBNT>;
+  using St = Streamer<FMT, CB, G, CPL, U, FULL, kBNT>;
   constexpr int R = St::R;
   constexpr int BR = kBIT * R;  // rows per block
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,8 +175,8 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
   const int nb = kBNW * nbw;
 
   SeedParams sp;
-  sp.xs = I.X;
-  sp.xexp = nullptr;
+  sp.xs = I.xs;
+  sp.xexp = I.xexp;
   sp.X = I.X;
   sp.D = I.D;
   sp.N = N;
@@ -199,7 +202,9 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
       for (int it = 0; it < kBIT; ++it) {
         const int64_t base = wb + (int64_t)(blk * kBIT + it) * R;
         if (base < we)
-          st.iter(sp, base, we, first, -1, [&](int64_t row, float dn, bool changed) {
+          // BF16 / FP8 rows: the row of the centre gets D = 0 (its FP32 row,
+          // not its stored one, is the centre)
+          st.iter(sp, base, we, first, FMT != FMT_F32 ? ci : -1, [&](int64_t row, float dn, bool changed) {
             if (changed) D[row] = dn;
             acc += (double)dn;
           });
@@ -351,34 +356,78 @@ __device__ __forceinline__ void run_member(const BPlan& P, int b, int r, BShared
   __syncthreads();
 }
 
+// The streamer of each (format, width): 16-byte chunks where the width
+// divides into them (G lanes per row), else one element per chunk.  Keep
+// rows_per_block() in step with these choices.  One kernel per row format
+// (each keeps only its own streamers' registers).
+template <int FMT>
 __device__ __forceinline__ void run_item(const BPlan& P, int b, int r, BShared& S) {
   const int d = P.inst[b].d;
-  switch (d) {
-    case 2: run_member<8, 1, 1, 8, true>(P, b, r, S); return;
-    case 4: run_member<16, 1, 1, 8, true>(P, b, r, S); return;
-    case 8: run_member<16, 2, 1, 8, true>(P, b, r, S); return;
-    case 16: run_member<16, 4, 1, 8, true>(P, b, r, S); return;
-    case 32: run_member<16, 8, 1, 8, true>(P, b, r, S); return;
-    case 64: run_member<16, 16, 1, 8, true>(P, b, r, S); return;
-    case 128: run_member<16, 32, 1, 8, true>(P, b, r, S); return;
-    default:
-      if (d <= 8)
-        run_member<4, 8, 1, 8, false>(P, b, r, S);
-      else if (d <= 64)
-        run_member<4, 64, 1, 8, false>(P, b, r, S);
-      else
-        run_member<4, 64, 4, 4, false>(P, b, r, S);
+  if constexpr (FMT == FMT_BF16) {
+    switch (d) {
+      case 8: run_member<FMT_BF16, 16, 1, 1, 8, true>(P, b, r, S); return;
+      case 16: run_member<FMT_BF16, 16, 2, 1, 8, true>(P, b, r, S); return;
+      case 32: run_member<FMT_BF16, 16, 4, 1, 8, true>(P, b, r, S); return;
+      case 64: run_member<FMT_BF16, 16, 8, 1, 8, true>(P, b, r, S); return;
+      case 128: run_member<FMT_BF16, 16, 16, 1, 8, true>(P, b, r, S); return;
+      default:
+        if (d <= 8)
+          run_member<FMT_BF16, 2, 8, 1, 8, false>(P, b, r, S);
+        else if (d <= 64)
+          run_member<FMT_BF16, 2, 64, 1, 8, false>(P, b, r, S);
+        else
+          run_member<FMT_BF16, 2, 64, 4, 4, false>(P, b, r, S);
+    }
+  } else if constexpr (FMT == FMT_FP8) {
+    switch (d) {
+      case 8: run_member<FMT_FP8, 8, 1, 1, 8, true>(P, b, r, S); return;
+      case 16: run_member<FMT_FP8, 16, 1, 1, 8, true>(P, b, r, S); return;
+      case 32: run_member<FMT_FP8, 16, 2, 1, 8, true>(P, b, r, S); return;
+      case 64: run_member<FMT_FP8, 16, 4, 1, 8, true>(P, b, r, S); return;
+      case 128: run_member<FMT_FP8, 16, 8, 1, 8, true>(P, b, r, S); return;
+      default:
+        if (d <= 8)
+          run_member<FMT_FP8, 1, 8, 1, 8, false>(P, b, r, S);
+        else if (d <= 64)
+          run_member<FMT_FP8, 1, 64, 1, 8, false>(P, b, r, S);
+        else
+          run_member<FMT_FP8, 1, 64, 4, 4, false>(P, b, r, S);
+    }
+  } else {
+    switch (d) {
+      case 2: run_member<FMT_F32, 8, 1, 1, 8, true>(P, b, r, S); return;
+      case 4: run_member<FMT_F32, 16, 1, 1, 8, true>(P, b, r, S); return;
+      case 8: run_member<FMT_F32, 16, 2, 1, 8, true>(P, b, r, S); return;
+      case 16: run_member<FMT_F32, 16, 4, 1, 8, true>(P, b, r, S); return;
+      case 32: run_member<FMT_F32, 16, 8, 1, 8, true>(P, b, r, S); return;
+      case 64: run_member<FMT_F32, 16, 16, 1, 8, true>(P, b, r, S); return;
+      case 128: run_member<FMT_F32, 16, 32, 1, 8, true>(P, b, r, S); return;
+      default:
+        if (d <= 8)
+          run_member<FMT_F32, 4, 8, 1, 8, false>(P, b, r, S);
+        else if (d <= 64)
+          run_member<FMT_F32, 4, 64, 1, 8, false>(P, b, r, S);
+        else
+          run_member<FMT_F32, 4, 64, 4, 4, false>(P, b, r, S);
+    }
   }
 }
 
+template <int FMT>
 __global__ __launch_bounds__(kBNT) void batched_kernel(BPlan P) {
   __shared__ BShared S;
   const int e = P.begin[blockIdx.x + 1];
   for (int it = P.begin[blockIdx.x]; it < e; ++it) {
     const BItem item = P.items[it];
-    run_item(P, item.b, item.r, S);
+    run_item<FMT>(P, item.b, item.r, S);
     __syncthreads();
   }
+}
+
+const void* batched_fn(int fmt) {
+  return fmt == FMT_BF16 ? reinterpret_cast<const void*>(&batched_kernel<FMT_BF16>)
+         : fmt == FMT_FP8 ? reinterpret_cast<const void*>(&batched_kernel<FMT_FP8>)
+                          : reinterpret_cast<const void*>(&batched_kernel<FMT_F32>);
 }
 
 __global__ void batched_reset_kernel(BPlan P) {
@@ -417,20 +466,21 @@ struct Layout {
   std::vector<int> gang;
 };
 
-int rows_per_block(int d) {
-  // R * kBIT for the streamer chosen in run_item
-  int G, U = 8;
-  switch (d) {
-    case 2: G = 1; break;
-    case 4: G = 1; break;
-    case 8: G = 2; break;
-    case 16: G = 4; break;
-    case 32: G = 8; break;
-    case 64: G = 16; break;
-    case 128: G = 32; break;
-    default:
-      G = d <= 8 ? 8 : 64;
-      if (d > 64) U = 4;
+int rows_per_block(int fmt, int d) {
+  // R * kBIT for the streamer chosen in run_item: G lanes per row, U loads
+  // per lane
+  int G = 0, U = 8;
+  const int eb = fmt == FMT_F32 ? 4 : fmt == FMT_BF16 ? 2 : 1;
+  // exact widths: bytes per chunk (8 for FP32 d = 2 and FP8 d = 8)
+  const int cb = (fmt == FMT_F32 && d == 2) || (fmt == FMT_FP8 && d == 8) ? 8 : 16;
+  const bool exact = fmt == FMT_F32 ? (d == 2 || d == 4 || d == 8 || d == 16 || d == 32 || d == 64 || d == 128)
+                                    : fmt == FMT_BF16 ? (d == 8 || d == 16 || d == 32 || d == 64 || d == 128)
+                                                      : (d == 8 || d == 16 || d == 32 || d == 64 || d == 128);
+  if (exact) {
+    G = d * eb / cb;
+  } else {
+    G = d <= 8 ? 8 : 64;
+    if (d > 64) U = 4;
   }
   return U * (64 / G) * kBIT;
 }
@@ -442,8 +492,13 @@ int num_cus() {
   return n;
 }
 
+int inst_fmt(const kmpp_instance& I) { return I.dtype == KMPP_BF16 ? FMT_BF16 : I.dtype == KMPP_FP8_E4M3 ? FMT_FP8 : FMT_F32; }
+
 double inst_time_us(const kmpp_instance& I, int w, const Tune& T, int W) {
-  const double bytes = (double)I.N * I.d * 4.0 * I.K;
+  // bytes streamed per seed step: the rows in their format (FP8: plus the
+  // exponent byte)
+  const double eb = I.dtype == KMPP_BF16 ? 2.0 : I.dtype == KMPP_FP8_E4M3 ? 1.0 + 1.0 / I.d : 4.0;
+  const double bytes = (double)I.N * I.d * eb * I.K;
   const double per_wg = T.chip_gbs * 1e3 / W;  // bytes per us per workgroup when all stream
   return bytes / w / per_wg + I.K * (w > 1 ? T.syncw_us : T.sync1_us);
 }
@@ -458,7 +513,8 @@ Layout plan_layout(const kmpp_instance* inst, int n, int W, const Tune& T) {
   L.n_items = 0;
   L.n_mslots = 0;
   for (int b = 0; b < n; ++b) {
-    const int64_t blocks1 = (inst[b].N + rows_per_block(inst[b].d) - 1) / rows_per_block(inst[b].d);
+    const int rpb = rows_per_block(inst_fmt(inst[b]), inst[b].d);
+    const int64_t blocks1 = (inst[b].N + rpb - 1) / rpb;
     int w = 1;
     // smallest gang within the time cap, enough LDS for the block sums, and
     // at least one block of rows per member
@@ -493,10 +549,18 @@ Layout plan_layout(const kmpp_instance* inst, int n, int W, const Tune& T) {
   return L;
 }
 
-int workgroups() {
+int workgroups(int fmt) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel, kBNT, 0) != hipSuccess || occ <= 0) occ = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_fn(fmt), kBNT, 0) != hipSuccess || occ <= 0)
+    occ = 1;
   return num_cus() * std::min(occ, g_tune.wg_per_cu);
+}
+
+// Every instance of a batch streams rows of one format (the first one's).
+bool one_format(const kmpp_instance* inst, int n) {
+  for (int b = 1; b < n; ++b)
+    if (inst[b].dtype != inst[0].dtype) return false;
+  return true;
 }
 
 // The budget of one gang wait, in ticks of the device's constant-rate
@@ -529,14 +593,17 @@ int batched_tune_set(const char* key, double v) {
 // member's block sums within LDS.
 bool batched_fits(const kmpp_instance& I) {
   if (I.N < 1 || I.K < 1 || I.K > I.N || I.d < 1 || I.d > kBMaxD || I.N > INT32_MAX) return false;
-  const int64_t blocks = (I.N + rows_per_block(I.d) - 1) / rows_per_block(I.d);
+  if (I.dtype != KMPP_F32 && I.dtype != KMPP_BF16 && I.dtype != KMPP_FP8_E4M3) return false;
+  const int rpb = rows_per_block(inst_fmt(I), I.d);
+  const int64_t blocks = (I.N + rpb - 1) / rpb;
   return blocks / kBMaxGang + kBNW <= kBMaxBlocks;
 }
 
 size_t batched_workspace(const kmpp_instance* inst, int n) {
   for (int b = 0; b < n; ++b)
     if (!batched_fits(inst[b])) return 0;
-  return plan_layout(inst, n, workgroups(), g_tune).total;
+  if (!one_format(inst, n)) return 0;
+  return plan_layout(inst, n, workgroups(inst_fmt(inst[0])), g_tune).total;
 }
 
 int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, size_t ws_bytes, hipStream_t stream) {
@@ -545,9 +612,14 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
     if (!I.X || !I.out_centers || I.N < 1 || I.K < 1 || I.K > I.N || I.N > INT32_MAX || I.d < 1 ||
         (reinterpret_cast<uintptr_t>(I.X) & 15))
       return KMPP_E_INVALID;
+    if (I.dtype != KMPP_F32 && I.dtype != KMPP_BF16 && I.dtype != KMPP_FP8_E4M3) return KMPP_E_INVALID;
+    if (I.dtype != KMPP_F32 && (!I.Xq || (reinterpret_cast<uintptr_t>(I.Xq) & 15))) return KMPP_E_INVALID;
+    if (I.dtype == KMPP_FP8_E4M3 && !I.Xq_exp) return KMPP_E_INVALID;
     if (!batched_fits(I)) return KMPP_E_UNSUPPORTED;
   }
-  const int W = workgroups();
+  if (!one_format(inst, n)) return KMPP_E_UNSUPPORTED;
+  const int fmt = inst_fmt(inst[0]);
+  const int W = workgroups(fmt);
   const Tune T = g_tune;
   const Layout L = plan_layout(inst, n, W, T);
   if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
@@ -571,6 +643,8 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
     const kmpp_instance& I = inst[b];
     BInst& H = hinst[b];
     H.X = I.X;
+    H.xs = I.dtype == KMPP_F32 ? static_cast<const void*>(I.X) : I.Xq;
+    H.xexp = I.dtype == KMPP_FP8_E4M3 ? I.Xq_exp : nullptr;
     H.C = I.out_centers;
     H.D = I.out_D ? I.out_D : reinterpret_cast<float*>(w + L.D) + offD;
     if (!I.out_D) offD += I.N;
@@ -627,6 +701,7 @@ int batched_prepare(const kmpp_instance* inst, int n, uint64_t seed, void* ws, s
   ph.plan.n_inst = n;
   ph.plan.W = W;
   ph.plan.n_mslots = L.n_mslots;
+  ph.plan.fmt = fmt;
   ph.cooperative = true;
   std::lock_guard<std::mutex> lk(g_mu);
   g_plans[ws] = ph;
@@ -648,10 +723,9 @@ int batched_launch(void* ws, hipStream_t stream) {
   if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return KMPP_E_HIP;
   hipError_t e;
   if (cs == hipStreamCaptureStatusNone)
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&batched_kernel), dim3(ph.W), dim3(kBNT), args, 0,
-                                   stream);
+    e = hipLaunchCooperativeKernel(batched_fn(ph.plan.fmt), dim3(ph.W), dim3(kBNT), args, 0, stream);
   else  // under capture: a plain launch of the same occupancy-sized grid
-    e = hipLaunchKernel(reinterpret_cast<const void*>(&batched_kernel), dim3(ph.W), dim3(kBNT), args, 0, stream);
+    e = hipLaunchKernel(batched_fn(ph.plan.fmt), dim3(ph.W), dim3(kBNT), args, 0, stream);
   return e == hipSuccess ? KMPP_OK : KMPP_E_HIP;
 }
 

@@ -93,6 +93,29 @@ def test_other_argument_checks_need_no_gpu(kl):
     assert L.kmpp_read_probe(fake, 1024, 4, 0, None, None) == -1
 
 
+def test_batched_dtype_checks_need_no_gpu(kl):
+    # a batch streams one row format; BF16 / FP8 instances need their stored
+    # rows (and FP8 its exponents); all refused before any HIP call (the
+    # pointers are never dereferenced on these paths)
+    fake = 1 << 20  # 16-byte aligned stand-in address
+    def inst(dtype, xq=fake, xe=fake):
+        return kl.Instance(fake, 1_000, 16, 4, fake, None, None, dtype, xq, xe)
+    L = kl.lib()
+    mixed = (kl.Instance * 2)(inst(0, None, None), inst(1))
+    assert L.kmpp_batched_workspace_bytes(mixed, 2) == 0
+    assert L.kmpp_seed_batched_prepare(mixed, 2, 0, fake, 1 << 30, None) == kl.E_UNSUPPORTED
+    for bad in (inst(1, xq=None), inst(1, xq=fake + 8), inst(2, xe=None), inst(7)):
+        one = (kl.Instance * 1)(bad)
+        assert L.kmpp_seed_batched_prepare(one, 1, 0, fake, 1 << 30, None) == kl.E_INVALID
+    with pytest.raises(ValueError, match="Xq"):
+        kl._instances([_cpu_rows()], [4], [(None, None, None)], kl.KMPP_BF16)
+
+
+def _cpu_rows():
+    import torch
+    return torch.zeros((10, 16))
+
+
 def test_tune_file_parses(kl, tmp_path):
     p = tmp_path / "t.txt"
     p.write_text("seed 0 32 256 512\nseed 0 64 512 256\n# comment\nseed 9 1 256 1\nbogus\n"

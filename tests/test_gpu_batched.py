@@ -129,6 +129,31 @@ def test_full_batched_workload(kl):
         print(f"  instances {b0}..{b0 + 63} replayed", flush=True)
 
 
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_precision_forms_batched(kl, dtype):
+    # BF16 / FP8 rows in the batched form: every width of the batched
+    # workload, a ragged odd width, and one instance large enough for a gang;
+    # each instance against the oracle on its dequantised rows (the centres
+    # are the FP32 rows, a drawn row's D is 0)
+    specs = [(200_000, 64, 64), (5_003, 16, 30), (3_001, 8, 25), (4_000, 13, 17), (2_500, 64, 40)]
+    Xs, Ks = _batch(specs, seed=7)
+    Q = [kl.kmpp_quantize(X, dtype) for X in Xs]
+    Xq = [q for q, _ in Q]
+    Xe = [e for _, e in Q] if dtype == 2 else None
+    print("batched precision form", dtype, flush=True)
+    outs, ws = kl.kmpp_seed_batched(Xs, Ks, 13, dtype=dtype, Xq=Xq, Xq_exp=Xe)
+    assert kl.kmpp_status(ws) == 0
+    for b in range(len(specs)):
+        C, D, I = outs[b]
+        Xh = Xs[b].cpu().numpy()
+        if dtype == 1:
+            Xd = oracle.bf16_decode(oracle.bf16_encode(Xh))
+        else:
+            Xd = oracle.fp8_dequantize_rows(*oracle.fp8_quantize_rows(Xh))
+        check_seed_run(Xh, Ks[b], 13, I.cpu().numpy(), C.cpu().numpy(), D.cpu().numpy(), Xd=Xd,
+                       zero_seed_rows=True, inst=b)
+
+
 def test_rejects_bad_instances(kl):
     X = torch.zeros((10, 300), device="cuda")
     with pytest.raises(kl.KmppError):
@@ -152,6 +177,8 @@ def test_degenerate_instance_warns(kl):
     Xs[3] = torch.ones((3_000, 8), device="cuda")
     outs, ws = kl.kmpp_seed_batched(Xs, Ks, 2)
     assert kl.kmpp_status(ws) == kl.W_DEGENERATE
+    # the same word read without a stream synchronisation (the work is done)
+    assert kl.kmpp_status_poll(ws) == kl.W_DEGENERATE
     _check_all(Xs, Ks, outs, 2)
 
 
@@ -160,6 +187,8 @@ def test_nonfinite_instance_errors(kl):
     Xs, Ks = _batch(specs, seed=8)
     Xs[5][17, 3] = float("nan")
     outs, ws = kl.kmpp_seed_batched(Xs, Ks, 2)
+    torch.cuda.synchronize()
+    assert kl.kmpp_status_poll(ws) == kl.E_NONFINITE
     assert kl.kmpp_status(ws) == kl.E_NONFINITE
     # the other instances are unaffected
     _check_all(Xs, Ks, outs, 2, which=[0, 1, 2, 3, 4, 6, 7])
