@@ -324,7 +324,9 @@ typedef struct kmpp_instance {
  * device-side barrier per seed; gangs are scheduled longest-first by a
  * host planner onto the co-resident workgroups.
  *
- * inst         HOST array [n_inst]
+ * inst         HOST array [n_inst]; every instance of one batch has the same
+ *              dtype (one launch streams one row format), else
+ *              KMPP_E_UNSUPPORTED (and a workspace size of 0)
  * kmpp_seed_batched_prepare: plans the schedule and uploads the descriptor
  *              table into the workspace (a synchronous host-to-device copy);
  * kmpp_seed_batched_launch:  enqueues only kernel launches and so may be
