@@ -21,6 +21,11 @@
 // writes: no cross-workgroup visibility of D is needed) and publishes the
 // index in a 64-bit flag tagged with the step.  Waits are bounded; an
 // expired wait sets KMPP_E_TIMEOUT.
+//
+// The rows streamed are FP32, BF16 or FP8 (one format per launch, a kernel
+// per format); the centres are always the FP32 rows, and with BF16 / FP8
+// rows the row of the current centre gets D = 0, as in the single-instance
+// seeding.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
