@@ -98,11 +98,12 @@ enum { KMPP_ROWS_CACHED = 0, KMPP_ROWS_NONTEMPORAL = 1, KMPP_ROWS_BUFFER = 2 };
 enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
 
 /*
- * Where each draw runs (kmpp_seed_opts.draw).  All follow the same steps
- * in the same order, so for one launch shape they pick the same seeds.
- *   KMPP_DRAW_AUTO    PASS where a pass has at most 256 tiles, else the
- *                     tuning table's choice for (format, d), else LEAD up to
- *                     4096 tiles, else KERNEL
+ * Where each draw runs (kmpp_seed_opts.draw).  PASS, KERNEL and LEAD follow
+ * the same steps in the same order, so for one launch shape they pick the
+ * same seeds.
+ *   KMPP_DRAW_AUTO    SINGLE where it applies, else PASS where a pass has
+ *                     at most 256 tiles, else the tuning table's choice for
+ *                     (format, d), else LEAD up to 4096 tiles, else KERNEL
  *   KMPP_DRAW_PASS    every workgroup of pass m+1 draws seed m at its start
  *                     from pass m's D and tile sums (one launch per seed;
  *                     passes then write D and tile sums to alternating
@@ -119,8 +120,20 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *                     already in flight).  One launch per seed, D and tile
  *                     sums in place.  Exact widths, unweighted seeding; else
  *                     KERNEL.
+ *   KMPP_DRAW_SINGLE  the whole loop (every pass and draw) in one
+ *                     1024-thread workgroup with the rows in LDS and D in
+ *                     registers: one launch per seeding.  Only for FP32
+ *                     rows, unweighted seeding, ceil(N / 1024) * d <= 24
+ *                     (so N <= 16384 and N * d <= 24576) and no other
+ *                     option set (threads, rows_per_tile,
+ *                     loads_per_lane, row_loads, centre_source, out_recheck,
+ *                     step_events), else KMPP_E_UNSUPPORTED; KMPP_DRAW_AUTO
+ *                     takes it wherever it applies.  Its FP64 partial sums
+ *                     run over each thread's rows rather than over tiles, so
+ *                     a draw within rounding of a row boundary may differ
+ *                     from the other placements'.
  */
-enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2, KMPP_DRAW_LEAD = 3 };
+enum { KMPP_DRAW_AUTO = 0, KMPP_DRAW_PASS = 1, KMPP_DRAW_KERNEL = 2, KMPP_DRAW_LEAD = 3, KMPP_DRAW_SINGLE = 4 };
 
 /* Optional knobs of kmpp_seed (pass NULL for defaults). */
 typedef struct kmpp_seed_opts {
@@ -140,8 +153,8 @@ typedef struct kmpp_seed_opts {
                            (profiling only) */
   int32_t centre_source;/* where the passes take the current centre from: 0 (default: LDS),
                            KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR or KMPP_CENTRE_GLOBAL */
-  int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS, KMPP_DRAW_KERNEL or
-                           KMPP_DRAW_LEAD */
+  int32_t draw;         /* KMPP_DRAW_AUTO (0, default), KMPP_DRAW_PASS, KMPP_DRAW_KERNEL,
+                           KMPP_DRAW_LEAD or KMPP_DRAW_SINGLE */
   double* out_sumD;     /* device FP64 [K] or NULL: [m] (m >= 1) = the sum of D that draw m
                            inverted (the denominator of P(n_l) in Algorithm 1, summed in
                            FP64 in the fixed tile order); [0] = 0 */

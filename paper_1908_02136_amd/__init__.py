@@ -28,7 +28,7 @@ KMPP_ROWS_CACHED, KMPP_ROWS_NONTEMPORAL, KMPP_ROWS_BUFFER = 0, 1, 2
 KMPP_CENTRE_LDS, KMPP_CENTRE_SCALAR, KMPP_CENTRE_GLOBAL = 1, 2, 3
 ROW_PATHS = {"cached": KMPP_ROWS_CACHED, "nontemporal": KMPP_ROWS_NONTEMPORAL, "buffer": KMPP_ROWS_BUFFER}
 CENTRE_SOURCES = {"lds": KMPP_CENTRE_LDS, "scalar": KMPP_CENTRE_SCALAR, "global": KMPP_CENTRE_GLOBAL}
-KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL, KMPP_DRAW_LEAD = 0, 1, 2, 3
+KMPP_DRAW_AUTO, KMPP_DRAW_PASS, KMPP_DRAW_KERNEL, KMPP_DRAW_LEAD, KMPP_DRAW_SINGLE = 0, 1, 2, 3, 4
 OK, W_DEGENERATE = 0, 1
 E_INVALID, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED, E_TIMEOUT, E_TOO_LARGE = -1, -2, -3, -4, -5, -6, -7
 MAX_D = 4096

@@ -138,12 +138,46 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
 
 size_t seed_workspace(int64_t N, int K) { return seed_layout(N, K).total; }
 
+// The one-workgroup loop applies: FP32 rows in LDS, unweighted, no option
+// that only the multi-workgroup passes honour.
+bool small_applies(int64_t N, int d, int dtype, const int32_t* wts, const kmpp_seed_opts* opts) {
+  if (dtype != KMPP_F32 || wts || !seed_small_fn(N, d)) return false;
+  return !(opts && (opts->threads || opts->rows_per_tile > 0 || opts->loads_per_lane > 0 || opts->row_loads >= 0 ||
+                    opts->centre_source || opts->out_recheck || opts->step_events));
+}
+
 int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t inst, uint32_t tag,
              const int32_t* wts, float* out_centers, float* out_D, int64_t* out_idx, const void* Xq,
              const int8_t* Xq_exp, int dtype, const kmpp_seed_opts* opts, void* workspace, size_t ws_bytes,
              hipStream_t stream, int32_t* status_out) {
   const SeedLayout L = seed_layout(N, K);
   if (ws_bytes < L.total) return KMPP_E_WORKSPACE;
+  const int want = opts ? opts->draw : KMPP_DRAW_AUTO;
+  const bool small = small_applies(N, d, dtype, wts, opts);
+  if (want == KMPP_DRAW_SINGLE && !small) return KMPP_E_UNSUPPORTED;
+  if (small && (want == KMPP_DRAW_SINGLE || want == KMPP_DRAW_AUTO)) {
+    char* ws = static_cast<char*>(workspace);
+    SeedParams p = {};
+    p.xs = X;
+    p.X = X;
+    p.centers = out_centers;
+    p.idx = out_idx ? out_idx : reinterpret_cast<int64_t*>(ws + L.idx);
+    p.D = out_D ? out_D : reinterpret_cast<float*>(ws + L.D);
+    p.ctl = reinterpret_cast<Ctl*>(ws);
+    p.N = N;
+    p.d = d;
+    p.K = K;
+    p.inst = inst;
+    p.seed = seed;
+    p.tag = tag;
+    p.sumD = opts ? opts->out_sumD : nullptr;
+    p.status_out = status_out;
+    void* args[] = {&p};
+    return hipLaunchKernel(seed_small_fn(N, d), dim3(1), dim3((unsigned)seed_small_threads()), args, 0, stream) ==
+                   hipSuccess
+               ? KMPP_OK
+               : KMPP_E_HIP;
+  }
   const SeedVariant* v = nullptr;
   int rpt = 0, ntiles = 0, draw = 0;
   const int rc = seed_pick_config(dtype, N, d, opts, &v, &rpt, &ntiles, &draw);
@@ -248,7 +282,7 @@ int kmpp_seed(const float* X, int64_t N, int32_t d, int32_t K, uint64_t seed, fl
     if (!Xq || !aligned(Xq, 16)) return KMPP_E_INVALID;
     if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
   }
-  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_LEAD)) return KMPP_E_INVALID;
+  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_SINGLE)) return KMPP_E_INVALID;
   return seed_run(X, N, d, K, seed, opts ? opts->instance : 0u, 0u, nullptr, out_centers, out_D, out_idx, Xq, Xq_exp,
                   dtype, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream_));
 }

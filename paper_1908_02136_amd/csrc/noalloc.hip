@@ -67,7 +67,7 @@ extern "C" int kmpp_seed_noalloc(const float* X, int64_t N, int32_t d, int32_t K
     if (!Xq || !aligned16(Xq)) return KMPP_E_INVALID;
     if (dtype == KMPP_FP8_E4M3 && !Xq_exp) return KMPP_E_INVALID;
   }
-  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_LEAD)) return KMPP_E_INVALID;
+  if (opts && (opts->draw < KMPP_DRAW_AUTO || opts->draw > KMPP_DRAW_SINGLE)) return KMPP_E_INVALID;
   if (N > KMPP_NOALLOC_MAX_N) return KMPP_E_TOO_LARGE;
   void* ws = nullptr;
   const int rc = scratch_on_current_device(&ws);

@@ -71,7 +71,7 @@ def test_seed_argument_checks_need_no_gpu(kl):
     # null outputs
     assert L.kmpp_seed(fake, 10, 2, 1, 0, None, None, None, None, None, 0, None, ws, 1 << 30, None) == -1
     # unknown draw mode
-    opts = kl.SeedOpts(0, 0, 0, 0, -1, None, None, 0, 4)
+    opts = kl.SeedOpts(0, 0, 0, 0, -1, None, None, 0, 5)
     assert L.kmpp_seed(fake, 10, 2, 1, 0, fake, None, None, None, None, 0, ctypes.byref(opts), ws, 1 << 30,
                        None) == -1
 

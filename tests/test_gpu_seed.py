@@ -209,16 +209,17 @@ def test_draw_at_pass_start_edge_cases(kl):
     assert np.all(D == 0.0)
 
 
-@pytest.mark.parametrize("draw", ["pass", "kernel", "lead"])
+@pytest.mark.parametrize("draw", ["pass", "kernel", "lead", "single"])
 def test_graph_capture_seed_and_assign(kl, draw):
     # seeding + assignment captured into a HIP graph and replayed three
     # times, outputs cleared eagerly between replays: every replay equals
     # the eager run (the draw at pass start alternates buffers by pass, fixed
     # per captured launch)
-    N, d, K = 150_001, 32, 40
+    N, d, K = (150_001, 32, 40) if draw != "single" else (12_001, 2, 40)
     Xh = kmpp_synth.gaussian(N, d, seed=15)
     X = Xh.cuda()
-    dm = {"pass": kl.KMPP_DRAW_PASS, "kernel": kl.KMPP_DRAW_KERNEL, "lead": kl.KMPP_DRAW_LEAD}[draw]
+    dm = {"pass": kl.KMPP_DRAW_PASS, "kernel": kl.KMPP_DRAW_KERNEL, "lead": kl.KMPP_DRAW_LEAD,
+          "single": kl.KMPP_DRAW_SINGLE}[draw]
     idx = torch.empty(K, dtype=torch.int64, device="cuda")
     C = torch.empty((K, d), dtype=torch.float32, device="cuda")
     D = torch.empty(N, dtype=torch.float32, device="cuda")
@@ -251,6 +252,63 @@ def test_graph_capture_seed_and_assign(kl, draw):
         for a, b in zip((idx, C, D, lab, mind), ref):
             assert torch.equal(a, b), f"replay {rep} differs"
     check_seed_run(Xh.numpy(), K, 8, idx.cpu().numpy(), C.cpu().numpy(), D.cpu().numpy())
+
+
+@pytest.mark.parametrize("N,d,K", [(10_000, 2, 16), (16_384, 1, 300), (3_001, 8, 100), (700, 23, 50),
+                                   (1_000, 24, 1), (5, 3, 5), (2_048, 12, 2_048)])
+def test_single_workgroup_seeding(kl, N, d, K):
+    # the whole loop in one workgroup: oracle parity (replay), the per-draw
+    # sums of D, the same results under the automatic choice, and seeds that
+    # mostly agree with the multi-workgroup passes (draws within rounding of
+    # a row boundary may differ: each is checked against the oracle)
+    Xh = kmpp_synth.gaussian(N, d, seed=N + d, scale=2.0)
+    X = Xh.cuda()
+    sD = torch.empty(K, dtype=torch.float64, device="cuda")
+    _say("single workgroup", N, d, K)
+    idx, C, D, st = run_seed(kl, X, K, seed=3, draw=kl.KMPP_DRAW_SINGLE, out_sumD=sD)
+    assert st == 0
+    r, _ = check_seed_run(Xh.numpy(), K, 3, idx, C, D)
+    sums = sD.cpu().numpy()
+    assert sums[0] == 0.0
+    if K > 1:
+        # the FP64 sums of the GPU's FP32 D against the oracle's FP64 totals
+        np.testing.assert_allclose(sums[1:], r.rec[1:K, oracle.REC_T], rtol=1e-5)
+    ia, Ca, Da, sta = run_seed(kl, X, K, seed=3)
+    assert sta == 0 and np.array_equal(ia, idx) and np.array_equal(Da, D)
+    ik, Ck, Dk, stk = run_seed(kl, X, K, seed=3, draw=kl.KMPP_DRAW_KERNEL)
+    assert stk == 0
+    assert np.mean(ik == idx) >= 0.9 or K <= 5
+
+
+def test_single_workgroup_edge_cases(kl):
+    S = kl.KMPP_DRAW_SINGLE
+    # zero sum of D: uniform draws and the warning, as in the oracle
+    Xh = torch.ones((1000, 8))
+    idx, C, D, st = run_seed(kl, Xh.cuda(), 5, seed=2, draw=S)
+    assert st == kl.W_DEGENERATE
+    assert idx.tolist() == oracle.seed(Xh.numpy(), 5, seed=2).idx.tolist()
+    # a NaN row: the error status
+    Xn = kmpp_synth.gaussian(1000, 8, seed=3)
+    Xn[17, 2] = float("nan")
+    assert run_seed(kl, Xn.cuda(), 5, seed=2, draw=S)[3] == kl.E_NONFINITE
+    # inputs it does not take: ceil(N / 1024) d > 24, more than 16384 rows,
+    # stored rows, a pass option
+    for shape, kw in (((3_000, 9), {}), ((16_385, 1), {}), ((1_000, 8), {"threads": 256})):
+        Xb = torch.zeros(shape, device="cuda")
+        with pytest.raises(kl.KmppError) as e:
+            kl.kmpp_seed(Xb, 4, 0, draw=S, **kw)
+        assert e.value.code == kl.E_UNSUPPORTED
+    Xq, _ = kl.kmpp_quantize(torch.randn((1_000, 8), device="cuda"), kl.KMPP_BF16)
+    with pytest.raises(kl.KmppError) as e:
+        kl.kmpp_seed(torch.randn((1_000, 8), device="cuda"), 4, 0, Xq=Xq, dtype=kl.KMPP_BF16, draw=S)
+    assert e.value.code == kl.E_UNSUPPORTED
+    # back-to-back runs on one workspace
+    Xg = kmpp_synth.gaussian(8_000, 3, seed=5)
+    ws = kl.workspace(kl.kmpp_seed_workspace_bytes(8_000, 3, 64), "cuda")
+    for K, seed in ((64, 1), (7, 2), (64, 1)):
+        idx, C, D, st = run_seed(kl, Xg.cuda(), K, seed=seed, ws=ws, draw=S)
+        assert st == 0
+        check_seed_run(Xg.numpy(), K, seed, idx, C, D)
 
 
 def test_K1_and_K_equals_N(kl):
