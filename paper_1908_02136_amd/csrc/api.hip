@@ -138,10 +138,10 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
 
 size_t seed_workspace(int64_t N, int K) { return seed_layout(N, K).total; }
 
-// The one-workgroup loop applies: FP32 rows in LDS, unweighted, no option
+// The one-workgroup loop applies: FP32 rows (and weights) in LDS, no option
 // that only the multi-workgroup passes honour.
 bool small_applies(int64_t N, int d, int dtype, const int32_t* wts, const kmpp_seed_opts* opts) {
-  if (dtype != KMPP_F32 || wts || !seed_small_fn(N, d)) return false;
+  if (dtype != KMPP_F32 || !seed_small_fn(N, d, wts != nullptr)) return false;
   return !(opts && (opts->threads || opts->rows_per_tile > 0 || opts->loads_per_lane > 0 || opts->row_loads >= 0 ||
                     opts->centre_source || opts->out_recheck || opts->step_events));
 }
@@ -170,10 +170,11 @@ int seed_run(const float* X, int64_t N, int d, int K, uint64_t seed, uint32_t in
     p.inst = inst;
     p.seed = seed;
     p.tag = tag;
+    p.wts = wts;
     p.sumD = opts ? opts->out_sumD : nullptr;
     p.status_out = status_out;
     void* args[] = {&p};
-    return hipLaunchKernel(seed_small_fn(N, d), dim3(1), dim3((unsigned)seed_small_threads()), args, 0, stream) ==
+    return hipLaunchKernel(seed_small_fn(N, d, wts != nullptr), dim3(1), dim3((unsigned)seed_small_threads()), args, 0, stream) ==
                    hipSuccess
                ? KMPP_OK
                : KMPP_E_HIP;

@@ -61,7 +61,7 @@ const std::vector<SeedVariant>& seed_variants();
 // 1024 threads in an LDS array of kSmallMaxElems FP32 values, at most 16
 // rows per thread: ceil(N / 1024) * d * 1024 <= kSmallMaxElems.
 constexpr int kSmallMaxElems = 24576;
-const void* seed_small_fn(int64_t N, int d);  // null where the input does not fit
+const void* seed_small_fn(int64_t N, int d, bool weighted);  // null where the input does not fit
 int seed_small_threads();
 const void* seed_init_fn();
 const void* seed_wfirst_fn();

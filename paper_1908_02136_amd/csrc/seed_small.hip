@@ -18,10 +18,11 @@
 //            whose inclusive prefix exceeds t is the seed (if rounding leaves
 //            none, the last row with D > 0); T = 0 draws uniformly
 //            (KMPP_W_DEGENERATE), a non-finite T raises KMPP_E_NONFINITE.
-// The draws follow the same definition as the other placements, but the
-// FP64 partial sums are taken over each thread's rows instead of over tiles,
-// so a draw that falls within rounding of a row boundary may pick the
-// neighbouring row.
+// Weighted seeding (the k-means|| recluster) draws in proportion to w D
+// (FP64 products), the first seed in proportion to w.  The draws follow the
+// same definition as the other placements, but the FP64 partial sums are
+// taken over each thread's rows instead of over tiles, so a draw that falls
+// within rounding of a row boundary may pick the neighbouring row.
 #include "kmpp_dev.h"
 #include "kmpp_impl.h"
 
@@ -71,13 +72,12 @@ __device__ __forceinline__ int small_ext(int b, int* sb) {
   return b;
 }
 
-template <int RMAX>
+template <int RMAX, bool WEIGHTED>
 __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
   __shared__ float xs[kSmallMaxElems];
   __shared__ double sh[kSmallNW];
   __shared__ int sb[kSmallNW];
   __shared__ int s_found[2];  // by draw parity: the smallest candidate row
-  __shared__ int64_t s_i0;
   const int tid = threadIdx.x;
   const int64_t N = p.N;
   const int d = p.d, K = p.K;
@@ -85,6 +85,8 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
   const int64_t r0 = min(N, (int64_t)tid * R);
   const int nr = (int)min((int64_t)R, N - r0);
   constexpr int NONE = INT_MAX;
+  // weighted seeding: the weights after the rows, interleaved the same way
+  const int* wl = reinterpret_cast<const int*>(xs) + R * d * kSmallNT;
 
   // row i = t R + r, value k -> xs[(r d + k) 1024 + t]
   for (int64_t e = tid; e < N * d; e += kSmallNT) {
@@ -93,12 +95,15 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
     const int t = (int)(i / R), r = (int)(i - (int64_t)t * R);
     xs[(r * d + k) * kSmallNT + t] = p.X[e];
   }
+  if constexpr (WEIGHTED) {
+    for (int64_t i = tid; i < N; i += kSmallNT) {
+      const int t = (int)(i / R), r = (int)(i - (int64_t)t * R);
+      reinterpret_cast<int*>(xs)[R * d * kSmallNT + r * kSmallNT + t] = p.wts[i];
+    }
+  }
   if (tid == 0) {
     p.ctl->status = KMPP_OK;
     if (p.sumD) p.sumD[0] = 0.0;
-    const int64_t i0 = uniform_index(draw_uniform(p.seed, 0u, p.inst, p.tag), N);
-    p.idx[0] = i0;
-    s_i0 = i0;
     s_found[0] = NONE;
     s_found[1] = NONE;
   }
@@ -106,8 +111,75 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
 
   float D[RMAX];
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r) D[r] = INFINITY;
-  int64_t cidx = s_i0;
+  for (int r = 0; r < RMAX; ++r) D[r] = 1.0f;  // the weighted first draw: shares w * 1
+  // a row's share of the draw: D, or w D in FP64
+  auto share = [&](int r) -> double {
+    if constexpr (WEIGHTED)
+      return (double)D[r] * (double)wl[r * kSmallNT + tid];
+    else
+      return (double)D[r];
+  };
+  // draw m from the current D (every thread returns the same row)
+  auto draw = [&](int m) -> int64_t {
+    double part = 0.0;
+    int lastpos = -1;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < nr) {
+        const double v = share(r);
+        part += v;
+        if (v > 0.0) lastpos = (int)r0 + r;
+      }
+    }
+    const double2 sc = small_scan(part, sh);
+    const double T = sc.y;
+    // the next draw's candidate slot (its last readers, in the previous
+    // draw, are past this draw's scan barriers)
+    if (tid == 0) s_found[(m + 1) & 1] = NONE;
+    const double u = draw_uniform(p.seed, (uint32_t)m, p.inst, p.tag);
+    if (tid == 0 && p.sumD) p.sumD[m] = T;
+    if (!isfinite(T)) {
+      if (tid == 0) raise_status(p.ctl, KMPP_E_NONFINITE);
+      return 0;
+    }
+    if (T == 0.0) {
+      if (tid == 0) raise_status(p.ctl, KMPP_W_DEGENERATE);
+      return uniform_index(u, N);
+    }
+    // the seed is the smallest candidate row over the workgroup (a thread's
+    // candidate: its first row whose inclusive prefix exceeds t).  Every
+    // thread past the owner of t has one (its first row), so the owner's
+    // candidate (the one thread with exclusive prefix <= t that finds one)
+    // is posted alone to an LDS minimum; only where rounding leaves the
+    // owner without one is the full minimum taken, and where no thread has
+    // one, the last row with a positive share.
+    const double t = __dmul_rn(u, T);
+    int found = NONE;
+    double run = sc.x;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      if (r < nr) {
+        run += share(r);
+        if (found == NONE && run > t) found = (int)r0 + r;
+      }
+    }
+    if (found != NONE && sc.x <= t) atomicMin(&s_found[m & 1], found);
+    __syncthreads();
+    int f = s_found[m & 1];
+    if (f == NONE) f = small_ext<true>(found, sb);
+    if (f != NONE) return f;
+    const int l = small_ext<false>(lastpos, sb);
+    return l >= 0 ? l : N - 1;
+  };
+
+  // the first seed: uniform, or (weighted) drawn in proportion to w
+  int64_t cidx;
+  if constexpr (WEIGHTED) {
+    cidx = draw(0);
+  } else {
+    cidx = uniform_index(draw_uniform(p.seed, 0u, p.inst, p.tag), N);
+  }
+  if (tid == 0) p.idx[0] = cidx;
   for (int m = 1; m <= K; ++m) {
     // pass m: centre m - 1 (row cidx = tc R + rc)
     const int tc = (int)(cidx / R), rc = (int)(cidx - (int64_t)tc * R);
@@ -127,65 +199,12 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
         a[r] = fmaf(df, df, a[r]);
       }
     }
-    double part = 0.0;
-    int lastpos = -1;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      if (r < nr) {
-        const float dn = m == 1 ? a[r] : fminf(D[r], a[r]);
-        D[r] = dn;
-        part += (double)dn;
-        if (dn > 0.0f) lastpos = (int)r0 + r;
-      }
-    }
+    for (int r = 0; r < RMAX; ++r)
+      if (r < nr) D[r] = m == 1 ? a[r] : fminf(D[r], a[r]);
     if (m == K) break;
-
-    // draw m
-    const double2 sc = small_scan(part, sh);
-    const double T = sc.y;
-    // the next draw's candidate slot (its last readers, in the previous
-    // draw, are past this draw's scan barriers)
-    if (tid == 0) s_found[(m + 1) & 1] = NONE;
-    const double u = draw_uniform(p.seed, (uint32_t)m, p.inst, p.tag);
-    if (tid == 0 && p.sumD) p.sumD[m] = T;
-    int64_t next;
-    if (!isfinite(T)) {
-      if (tid == 0) raise_status(p.ctl, KMPP_E_NONFINITE);
-      next = 0;
-    } else if (T == 0.0) {
-      if (tid == 0) raise_status(p.ctl, KMPP_W_DEGENERATE);
-      next = uniform_index(u, N);
-    } else {
-      // the seed is the smallest candidate row over the workgroup (a thread's
-      // candidate: its first row whose inclusive prefix exceeds t).  Every
-      // thread past the owner of t has one (its first row), so the owner's
-      // candidate (the one thread with exclusive prefix <= t that finds
-      // one) is posted alone to an LDS minimum; only where rounding leaves
-      // the owner without one is the full minimum taken, and where no
-      // thread has one, the last row with D > 0.
-      const double t = __dmul_rn(u, T);
-      int found = NONE;
-      double run = sc.x;
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r) {
-        if (r < nr) {
-          run += (double)D[r];
-          if (found == NONE && run > t) found = (int)r0 + r;
-        }
-      }
-      if (found != NONE && sc.x <= t) atomicMin(&s_found[m & 1], found);
-      __syncthreads();
-      int f = s_found[m & 1];
-      if (f == NONE) f = small_ext<true>(found, sb);
-      if (f != NONE) {
-        next = f;
-      } else {
-        const int l = small_ext<false>(lastpos, sb);
-        next = l >= 0 ? l : N - 1;
-      }
-    }
-    if (tid == 0) p.idx[m] = next;
-    cidx = next;
+    cidx = draw(m);
+    if (tid == 0) p.idx[m] = cidx;
   }
 #pragma unroll
   for (int r = 0; r < RMAX; ++r)
@@ -196,16 +215,22 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
   }
 }
 
-// The kernel for N rows of width d, or null where the interleaved rows
-// (R d 1024 values) would not fit the LDS array or R exceeds 16 (16 rows
-// per thread already spill a few registers to scratch; 24 spilled more).
-const void* seed_small_fn(int64_t N, int d) {
+// The kernel for N rows of width d (weighted: plus a weight per row), or
+// null where the interleaved rows (R (d + weighted) 1024 values) would not
+// fit the LDS array or R exceeds 16 (16 rows per thread already spill a few
+// registers to scratch; 24 spilled more).
+const void* seed_small_fn(int64_t N, int d, bool weighted) {
   const int64_t R = (N + kSmallNT - 1) / kSmallNT;
-  if (R * d * kSmallNT > kSmallMaxElems) return nullptr;
-  if (R <= 4) return reinterpret_cast<const void*>(&seed_small_kernel<4>);
-  if (R <= 8) return reinterpret_cast<const void*>(&seed_small_kernel<8>);
-  if (R <= 12) return reinterpret_cast<const void*>(&seed_small_kernel<12>);
-  if (R <= 16) return reinterpret_cast<const void*>(&seed_small_kernel<16>);
+  if (R * (d + (weighted ? 1 : 0)) * kSmallNT > kSmallMaxElems) return nullptr;
+#define KMPP_SMALL(RM)                                                                                \
+  if (R <= RM)                                                                                        \
+    return weighted ? reinterpret_cast<const void*>(&seed_small_kernel<RM, true>)                     \
+                    : reinterpret_cast<const void*>(&seed_small_kernel<RM, false>);
+  KMPP_SMALL(4)
+  KMPP_SMALL(8)
+  KMPP_SMALL(12)
+  KMPP_SMALL(16)
+#undef KMPP_SMALL
   return nullptr;
 }
 int seed_small_threads() { return kSmallNT; }
