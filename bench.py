@@ -672,8 +672,8 @@ def main():
     ap.add_argument("--seed-k", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
-              "described in DESIGN.md, not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this library runs on one GPU; "
+              "sharding the rows over several GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
