@@ -93,6 +93,21 @@ def test_other_argument_checks_need_no_gpu(kl):
     assert L.kmpp_read_probe(fake, 1024, 4, 0, None, None) == -1
 
 
+def test_single_workgroup_limits_need_no_gpu(kl):
+    # KMPP_DRAW_SINGLE refuses what one workgroup cannot hold (more than 24
+    # interleaved values per thread, more than 16384 rows, stored rows, a
+    # pass option) before any HIP call
+    L = kl.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    ws = ctypes.c_void_p(1 << 24)
+    for N, d, kw, dtype in ((3_000, 9, {}, 0), (16_385, 1, {}, 0), (1_000, 8, {"threads": 256}, 0),
+                            (1_000, 8, {}, 1)):
+        opts = kl.SeedOpts(0, kw.get("threads", 0), 0, 0, -1, None, None, 0, kl.KMPP_DRAW_SINGLE)
+        xq = fake if dtype else None
+        assert L.kmpp_seed(fake, N, d, 4, 0, fake, None, None, xq, None, dtype, ctypes.byref(opts), ws, 1 << 30,
+                           None) == kl.E_UNSUPPORTED, (N, d, kw, dtype)
+
+
 def test_batched_dtype_checks_need_no_gpu(kl):
     # a batch streams one row format; BF16 / FP8 instances need their stored
     # rows (and FP8 its exponents); all refused before any HIP call (the
