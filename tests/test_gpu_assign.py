@@ -223,20 +223,22 @@ def test_first_stage_bound_covers_high_part_rounding(kl, dtype, d):
     check_assign(Xd, C.float().numpy(), lab, mind)
 
 
+@pytest.mark.parametrize("K", [66, 320])
 @pytest.mark.parametrize("d", [16, 64])
-def test_short_recheck_queue_ties_and_nan(kl, d):
+def test_short_recheck_queue_ties_and_nan(kl, d, K):
     # every row goes to the recheck (all near one far point), and the queue
     # is short enough for its centre tiles to be split over workgroups: the
     # second half of the centres repeats the first, so each row's best
     # distance is reached in two different tile ranges and the smaller index
-    # must win; a NaN row still gets label -1
-    N, K = 5_003, 320
+    # must win; a NaN row still gets label -1 (K = 66: three centre tiles,
+    # the last one partial, in two ranges)
+    N = 5_003
     g = torch.Generator().manual_seed(d)
     Ch = (500.0 + torch.randn((K // 2, d), generator=g)).float()
     Ch = torch.cat([Ch, Ch]).contiguous()
     Xh = (500.0 + torch.randn((N, d), generator=g)).float()
     Xh[4_321, 3] = float("nan")
-    print("assign short recheck queue ties", d, flush=True)
+    print("assign short recheck queue ties", d, K, flush=True)
     for out_mind in (None, False):
         lab, mind, _ = kl.kmpp_assign(Xh.cuda(), Ch.cuda(), out_mind=out_mind)
         torch.cuda.synchronize()
