@@ -72,12 +72,70 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const float* __restrict_
   }
 }
 
+// Widths that are a multiple of 4, up to 256: G lanes per row, each holding
+// one 16-byte chunk (G = the power of two >= d / 4), so the row is read
+// once; max |x| is reduced over the row's G lanes, and U row groups per lane
+// are loaded before any is converted.  Same arithmetic as quant_fp8_kernel.
+template <int G>
+__global__ __launch_bounds__(256) void quant_fp8_rows_kernel(const float* __restrict__ X, uint8_t* __restrict__ Q,
+                                                             int8_t* __restrict__ E, int64_t N, int d) {
+  constexpr int U = 4;
+  constexpr int RPW = 64 / G;  // rows per wave and row group
+  const int lane = threadIdx.x & 63, sub = lane % G, rg = lane / G;
+  const int nc = d / 4;        // chunks per row (<= G)
+  const bool mine = sub < nc;
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t base = wave0 * RPW * U; base < N; base += waves * RPW * U) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = base + (int64_t)u * RPW + rg;
+      // rows past N and lanes past the row read an in-bounds chunk, unused
+      const int64_t rr = r < N ? r : N - 1;
+      v[u] = *reinterpret_cast<const float4*>(X + rr * d + 4 * (mine ? sub : 0));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = base + (int64_t)u * RPW + rg;
+      float amax = mine ? fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))) : 0.0f;
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+      const int e = fp8_row_exponent(amax);
+      if (r < N) {
+        if (sub == 0) E[r] = (int8_t)e;
+        if (mine) {
+          int w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(v[u].x, -e), ldexpf(v[u].y, -e), 0, false);
+          w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(v[u].z, -e), ldexpf(v[u].w, -e), w, true);
+          *reinterpret_cast<uint32_t*>(Q + r * d + 4 * sub) = (uint32_t)w;
+        }
+      }
+    }
+  }
+}
+
 int launch_quantize(const float* X, int64_t N, int d, int dtype, void* Xq, int8_t* Xq_exp, hipStream_t stream) {
   const int64_t n = N * (int64_t)d;
   if (dtype == KMPP_BF16) {
     const int64_t blocks = std::min<int64_t>(65536, (n / 4 + 255) / 256 + 1);
     hipLaunchKernelGGL(quant_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X,
                        static_cast<uint16_t*>(Xq), n);
+  } else if ((d & 3) == 0 && d <= 256) {
+    int g = 1;
+    while (g < d / 4) g <<= 1;
+    // rows per workgroup per loop step: 4 waves x (64 / g) rows x 4 row groups
+    const int64_t rows_per_block = 4 * (64 / g) * 4;
+    const int64_t blocks = std::min<int64_t>(65536, (N + rows_per_block - 1) / rows_per_block);
+    uint8_t* q = static_cast<uint8_t*>(Xq);
+    switch (g) {
+      case 1: hipLaunchKernelGGL(quant_fp8_rows_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      case 2: hipLaunchKernelGGL(quant_fp8_rows_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      case 4: hipLaunchKernelGGL(quant_fp8_rows_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      case 8: hipLaunchKernelGGL(quant_fp8_rows_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      case 16: hipLaunchKernelGGL(quant_fp8_rows_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      case 32: hipLaunchKernelGGL(quant_fp8_rows_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+      default: hipLaunchKernelGGL(quant_fp8_rows_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, stream, X, q, Xq_exp, N, d); break;
+    }
   } else {
     const int64_t blocks = std::min<int64_t>(65536, (N + 3) / 4);
     hipLaunchKernelGGL(quant_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X,

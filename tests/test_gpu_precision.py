@@ -37,7 +37,8 @@ def test_bf16_quantiser_bit_exact(kl, d):
     np.testing.assert_array_equal(got, oracle.bf16_encode(Xh.numpy()))
 
 
-@pytest.mark.parametrize("d,scale", [(5, 1.0), (64, 100.0), (128, 0.01), (64, 1e-30)])
+@pytest.mark.parametrize("d,scale", [(5, 1.0), (64, 100.0), (128, 0.01), (64, 1e-30), (4, 3.0), (8, 3.0),
+                                     (12, 3.0), (256, 3.0), (260, 3.0)])
 def test_fp8_quantiser_bit_exact(kl, d, scale):
     Xh = kmpp_synth.gaussian(4_001, d, seed=d, scale=scale)
     Xh[3] = 0.0                    # all-zero row: exponent 0
