@@ -56,6 +56,8 @@ def test_two_calls_second_smaller(kl):
     a = _noalloc(kl, big.X, big.K, 0)
     assert a[3] == 0
     _same(a, _with_ws(kl, big.X, big.K, 0))
+    # (10,000 x 2 fits one workgroup's LDS: the automatic placement runs
+    # the whole loop in one workgroup, on the array's status word too)
     small = kmpp_synth.small()
     print("noalloc: small N=10000 d=2 K=16 (after the large call)", flush=True)
     b = _noalloc(kl, small.X.cuda(), small.K, 3)
