@@ -61,7 +61,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+# dense matrix peaks; FP8 rows are judged against the FP8 peak
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 
 def _log(*a):
@@ -361,10 +362,6 @@ def small_latency(kl, kmpp_synth, reps=50):
     return {"workload": f"small N={w.N} d={w.d} K={K}", "seed_us": seed_us, "step_us": step_us,
             "status": kl.kmpp_status(ws)}
 
-
-
-
-MFMA_PEAK_TFLOPS["fp8"] = 5000.0   # dense FP8 matrix peak: the ceiling FP8 rows are judged against
 
 
 SEED_SOURCES = ["paper_1908_02136_amd/csrc/seed.hip", "paper_1908_02136_amd/csrc/stream.h",
