@@ -8,7 +8,7 @@ import torch
 
 import kmpp_synth
 import oracle
-from gpu_util import check_D, check_seed_run
+from gpu_util import check_seed_run
 
 pytestmark = pytest.mark.gpu
 

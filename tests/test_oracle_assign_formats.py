@@ -9,7 +9,6 @@ for its storage formats used by the precision forms.
   float8_e4m3fn conversion; per-row power-of-two exponent rule.
 """
 import numpy as np
-import pytest
 import torch
 
 import oracle

@@ -21,7 +21,6 @@ import math
 from fractions import Fraction
 
 import numpy as np
-import pytest
 import torch
 
 import kmpp_synth
