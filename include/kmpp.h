@@ -123,8 +123,8 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *   KMPP_DRAW_SINGLE  the whole loop (every pass and draw) in one
  *                     1024-thread workgroup with the rows in LDS and D in
  *                     registers: one launch per seeding.  Only for FP32
- *                     rows, unweighted seeding, ceil(N / 1024) * d <= 24
- *                     (so N <= 16384 and N * d <= 24576) and no other
+ *                     rows, unweighted seeding, ceil(N / 1024) * d <= 36
+ *                     (so N <= 16384 and N * d <= 36864) and no other
  *                     option set (threads, rows_per_tile,
  *                     loads_per_lane, row_loads, centre_source, out_recheck,
  *                     step_events), else KMPP_E_UNSUPPORTED; KMPP_DRAW_AUTO

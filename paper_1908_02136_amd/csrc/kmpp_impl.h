@@ -60,7 +60,7 @@ const std::vector<SeedVariant>& seed_variants();
 // The one-workgroup seed loop (seed_small.hip): the rows interleaved over
 // 1024 threads in an LDS array of kSmallMaxElems FP32 values, at most 16
 // rows per thread: ceil(N / 1024) * d * 1024 <= kSmallMaxElems.
-constexpr int kSmallMaxElems = 24576;
+constexpr int kSmallMaxElems = 36864;
 const void* seed_small_fn(int64_t N, int d, bool weighted);  // null where the input does not fit
 int seed_small_threads();
 const void* seed_init_fn();

@@ -217,8 +217,8 @@ __global__ __launch_bounds__(kSmallNT) void seed_small_kernel(SeedParams p) {
 
 // The kernel for N rows of width d (weighted: plus a weight per row), or
 // null where the interleaved rows (R (d + weighted) 1024 values) would not
-// fit the LDS array or R exceeds 16 (16 rows per thread already spill a few
-// registers to scratch; 24 spilled more).
+// fit the LDS array or R exceeds 16 (24 rows per thread spilled D to
+// scratch).
 const void* seed_small_fn(int64_t N, int d, bool weighted) {
   const int64_t R = (N + kSmallNT - 1) / kSmallNT;
   if (R * (d + (weighted ? 1 : 0)) * kSmallNT > kSmallMaxElems) return nullptr;

@@ -94,13 +94,13 @@ def test_other_argument_checks_need_no_gpu(kl):
 
 
 def test_single_workgroup_limits_need_no_gpu(kl):
-    # KMPP_DRAW_SINGLE refuses what one workgroup cannot hold (more than 24
+    # KMPP_DRAW_SINGLE refuses what one workgroup cannot hold (more than 36
     # interleaved values per thread, more than 16384 rows, stored rows, a
     # pass option) before any HIP call
     L = kl.lib()
     fake = ctypes.c_void_p(1 << 20)
     ws = ctypes.c_void_p(1 << 24)
-    for N, d, kw, dtype in ((3_000, 9, {}, 0), (16_385, 1, {}, 0), (1_000, 8, {"threads": 256}, 0),
+    for N, d, kw, dtype in ((3_000, 13, {}, 0), (16_385, 1, {}, 0), (1_000, 8, {"threads": 256}, 0),
                             (1_000, 8, {}, 1)):
         opts = kl.SeedOpts(0, kw.get("threads", 0), 0, 0, -1, None, None, 0, kl.KMPP_DRAW_SINGLE)
         xq = fake if dtype else None

@@ -255,7 +255,8 @@ def test_graph_capture_seed_and_assign(kl, draw):
 
 
 @pytest.mark.parametrize("N,d,K", [(10_000, 2, 16), (16_384, 1, 300), (3_001, 8, 100), (700, 23, 50),
-                                   (1_000, 24, 1), (5, 3, 5), (2_048, 12, 2_048)])
+                                   (1_000, 24, 1), (5, 3, 5), (2_048, 12, 2_048),
+                                   (4_096, 9, 100), (12_000, 3, 200), (1_024, 36, 64)])
 def test_single_workgroup_seeding(kl, N, d, K):
     # the whole loop in one workgroup: oracle parity (replay), the per-draw
     # sums of D, the same results under the automatic choice, and seeds that
@@ -291,9 +292,9 @@ def test_single_workgroup_edge_cases(kl):
     Xn = kmpp_synth.gaussian(1000, 8, seed=3)
     Xn[17, 2] = float("nan")
     assert run_seed(kl, Xn.cuda(), 5, seed=2, draw=S)[3] == kl.E_NONFINITE
-    # inputs it does not take: ceil(N / 1024) d > 24, more than 16384 rows,
+    # inputs it does not take: ceil(N / 1024) d > 36, more than 16384 rows,
     # stored rows, a pass option
-    for shape, kw in (((3_000, 9), {}), ((16_385, 1), {}), ((1_000, 8), {"threads": 256})):
+    for shape, kw in (((3_000, 13), {}), ((16_385, 1), {}), ((1_000, 8), {"threads": 256})):
         Xb = torch.zeros(shape, device="cuda")
         with pytest.raises(kl.KmppError) as e:
             kl.kmpp_seed(Xb, 4, 0, draw=S, **kw)
