@@ -79,20 +79,16 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
   int nt = 256, rpt = 0, u = 8, tuned_draw = 0;
   int ntl = (int64_t)N * d * elem_bytes(dtype) > kCachedRowBytes ? 1 : 0;
   SeedTune t;
-  bool rpt_tuned = false;
   if (tuned(dtype, d, &t)) {
     nt = t.threads;
     rpt = t.rpt;
-    rpt_tuned = true;
     if (t.u > 0) u = t.u;
     if (t.ntl >= 0) ntl = t.ntl;
     tuned_draw = t.draw;
   }
   if (opts && opts->threads) nt = opts->threads;
-  if (opts && opts->rows_per_tile > 0) {
-    rpt = opts->rows_per_tile;
-    rpt_tuned = false;
-  }
+  const bool caller_rpt = opts && opts->rows_per_tile > 0;
+  if (caller_rpt) rpt = opts->rows_per_tile;
   if (opts && opts->loads_per_lane > 0) u = opts->loads_per_lane;
   if (opts && opts->row_loads >= 0) ntl = opts->row_loads;
   int cs = CEN_LDS;
@@ -107,10 +103,12 @@ int seed_pick_config(int dtype, int64_t N, int d, const kmpp_seed_opts* opts, co
     const int64_t row_bytes = (int64_t)d * elem_bytes(dtype);
     rpt = (int)std::max<int64_t>(it, (65536 / std::max<int64_t>(1, row_bytes)) / it * it);
   }
-  // a tuned tile (chosen at one size per format and width) is shrunk where
-  // it would leave fewer than kMinTiles tiles, so smaller inputs still spread
-  // over the chip
-  if (rpt_tuned) rpt = (int)std::min<int64_t>(rpt, std::max<int64_t>(it, (N + kMinTiles - 1) / kMinTiles));
+  // a tuned tile (chosen at one size per format and width) or the default
+  // one is shrunk where it would leave fewer than kMinTiles tiles, so
+  // smaller inputs still spread over the chip (unshrunk 64 KiB tiles give
+  // 20,000 x 9 rows 11 workgroups: 21 us per seed, against 6.8 us for the
+  // tuned width 8)
+  if (!caller_rpt) rpt = (int)std::min<int64_t>(rpt, std::max<int64_t>(it, (N + kMinTiles - 1) / kMinTiles));
   int64_t r = ((int64_t)rpt + it - 1) / it * it;
   const int64_t min_r = (N + kMaxTiles - 1) / kMaxTiles;
   if (r < min_r) r = (min_r + it - 1) / it * it;
