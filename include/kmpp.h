@@ -108,7 +108,8 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *                     from pass m's D and tile sums (one launch per seed;
  *                     passes then write D and tile sums to alternating
  *                     buffers, every row's D each pass).  Used where it
- *                     applies (unweighted seeding, exact widths, at most 2048
+ *                     applies (unweighted seeding, FP32 rows of any width
+ *                     or BF16 / FP8 rows of exact widths, at most 2048
  *                     tiles, the tile sums or one tile's D within the LDS
  *                     share that keeps the pass's occupancy), else KERNEL.
  *   KMPP_DRAW_KERNEL  a one-workgroup draw kernel after each pass (two
@@ -118,8 +119,8 @@ enum { KMPP_CENTRE_LDS = 1, KMPP_CENTRE_SCALAR = 2, KMPP_CENTRE_GLOBAL = 3 };
  *                     for it (bounded: KMPP_E_TIMEOUT after one second, see
  *                     kmpp_tune_load; narrow FP32 rows with their first rows
  *                     already in flight).  One launch per seed, D and tile
- *                     sums in place.  Exact widths, unweighted seeding; else
- *                     KERNEL.
+ *                     sums in place.  The same rows as PASS, unweighted
+ *                     seeding; else KERNEL.
  *   KMPP_DRAW_SINGLE  the whole loop (every pass and draw) in one
  *                     1024-thread workgroup with the rows in LDS and D in
  *                     registers: one launch per seeding.  Only for FP32

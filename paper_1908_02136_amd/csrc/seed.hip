@@ -584,14 +584,15 @@ static SeedVariant make_variant(int dexact) {
       make_variant<FMT_FP8, 16, 16, 1, 8, true, NT, L, CEN_LDS, true>(256),                                                \
       make_variant<FMT_FP8, 16, 4, 1, 16, true, NT, L, CEN_LDS, true>(64), make_variant<FMT_FP8, 16, 8, 1, 16, true, NT, L, CEN_LDS, true>(128)
 
-// Any d: one element per chunk, G = min(64, pow2 >= d) lanes per row.
+// Any d: one element per chunk, G = min(64, pow2 >= d) lanes per row; FP32
+// rows also with the drawer.
 #define KMPP_GENERIC(NT)                                                                                    \
-  make_variant<FMT_F32, 4, 1, 1, 8, false, NT, ROW_CACHED>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT, ROW_CACHED>(-2), \
-      make_variant<FMT_F32, 4, 4, 1, 8, false, NT, ROW_CACHED>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT, ROW_CACHED>(-8), \
-      make_variant<FMT_F32, 4, 16, 1, 8, false, NT, ROW_CACHED>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT, ROW_CACHED>(-32), \
-      make_variant<FMT_F32, 4, 64, 1, 8, false, NT, ROW_CACHED>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT, ROW_CACHED>(-256), \
-      make_variant<FMT_F32, 4, 64, 16, 2, false, NT, ROW_CACHED>(-1024),                                         \
-      make_variant<FMT_F32, 4, 64, 64, 1, false, NT, ROW_CACHED>(-4096),                                         \
+  make_variant<FMT_F32, 4, 1, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-1), make_variant<FMT_F32, 4, 2, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-2), \
+      make_variant<FMT_F32, 4, 4, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-4), make_variant<FMT_F32, 4, 8, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-8), \
+      make_variant<FMT_F32, 4, 16, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-16), make_variant<FMT_F32, 4, 32, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-32), \
+      make_variant<FMT_F32, 4, 64, 1, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-64), make_variant<FMT_F32, 4, 64, 4, 8, false, NT, ROW_CACHED, CEN_LDS, true>(-256), \
+      make_variant<FMT_F32, 4, 64, 16, 2, false, NT, ROW_CACHED, CEN_LDS, true>(-1024),                                         \
+      make_variant<FMT_F32, 4, 64, 64, 1, false, NT, ROW_CACHED, CEN_LDS, true>(-4096),                                         \
       make_variant<FMT_BF16, 2, 1, 1, 8, false, NT, ROW_CACHED>(-1), make_variant<FMT_BF16, 2, 2, 1, 8, false, NT, ROW_CACHED>(-2), \
       make_variant<FMT_BF16, 2, 4, 1, 8, false, NT, ROW_CACHED>(-4), make_variant<FMT_BF16, 2, 8, 1, 8, false, NT, ROW_CACHED>(-8), \
       make_variant<FMT_BF16, 2, 16, 1, 8, false, NT, ROW_CACHED>(-16), make_variant<FMT_BF16, 2, 32, 1, 8, false, NT, ROW_CACHED>(-32), \

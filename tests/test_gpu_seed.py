@@ -114,6 +114,30 @@ def test_lead_draw_matches_other_placements(kl, threads, rpt, K):
     check_seed_run(Xh.numpy(), K, 5, a[0], a[1], a[2])
 
 
+@pytest.mark.parametrize("d,rpt", [(3, 0), (9, 0), (31, 64), (100, 0), (9, 5000)])
+def test_generic_width_draw_placements(kl, d, rpt):
+    # FP32 widths without an exact-width pass (one value per lane, masked
+    # lanes) with the draw at pass start and the lead draw: at 256 threads
+    # the same seeds and D as the draw kernel, and the oracle's.  rpt=5000
+    # at d=9 leaves the draw at pass start its LDS share (tile D staged)
+    N, K = 40_001, 30
+    Xh = kmpp_synth.gaussian(N, d, seed=31 + d, scale=2.0)
+    X = Xh.cuda()
+    _say("generic width draw placements", N, d, K, rpt)
+    b = run_seed(kl, X, K, seed=6, threads=256, rows_per_tile=rpt, draw=kl.KMPP_DRAW_KERNEL)
+    assert b[3] == 0
+    for draw in (kl.KMPP_DRAW_PASS, kl.KMPP_DRAW_LEAD):
+        a = run_seed(kl, X, K, seed=6, threads=256, rows_per_tile=rpt, draw=draw)
+        assert a[3] == 0
+        assert np.array_equal(a[0], b[0]), draw
+        assert np.array_equal(a[2], b[2]), draw
+    check_seed_run(Xh.numpy(), K, 6, b[0], b[1], b[2])
+    # the automatic choice (tiles shrunk for this size, draw by placement)
+    c = run_seed(kl, X, K, seed=6)
+    assert c[3] == 0
+    check_seed_run(Xh.numpy(), K, 6, c[0], c[1], c[2])
+
+
 def test_lead_draw_edge_cases_and_repeats(kl):
     # a zero sum of D (uniform draws, warning), a NaN row (error), K=1, K=2,
     # K=N, and back-to-back runs on one workspace (the published index is
